@@ -1,0 +1,202 @@
+"""FP64 CPU oracle for the relativistic-hydrodynamics hot path (test infrastructure).
+
+Plain, slow reference implementation of the operator L(u) of Eq. (2) of
+Sikorski et al. (arXiv:1604.03360, Sec. 1), its finite-difference WENO5/WENO7
+flux reconstruction (Sec. 1.2) and the third-order Runge-Kutta integration
+(Sec. 1), plus the analytic references used by the tests: the exact conformal
+Riemann solution of the shock tube and the Hubble-like flow (Sec. 3).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+``paper_1604_03360_amd`` and never imports it.
+
+The arithmetic lives in ``rh_oracle.cpp`` (C++17, FP64, built with
+``-ffp-contract=off`` so that every expression is evaluated as written).  This
+module only marshals numpy arrays through ctypes.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rh_oracle.cpp")
+_LIB = os.path.join(_HERE, "librh_oracle.so")
+
+BC_PERIODIC, BC_OUTFLOW, BC_HUBBLE = 0, 1, 2
+
+
+def build(force=False):
+    """Compile the oracle shared library with g++ (OpenMP over grid lines)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+               "-shared", _SRC, "-o", _LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class OrcGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("h", ctypes.c_double * 3), ("c0", ctypes.c_double * 3),
+                ("order", ctypes.c_int), ("bc", ctypes.c_int * 3), ("eps", ctypes.c_double),
+                ("hub", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lp = ctypes.POINTER(ctypes.c_long)
+        gp = ctypes.POINTER(OrcGrid)
+        L.orc_prim2con.argtypes = [ctypes.c_long, dp, dp]
+        L.orc_con2prim.argtypes = [ctypes.c_long, dp, dp, lp]
+        L.orc_flux.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp]
+        L.orc_weno.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int]
+        L.orc_weno.restype = ctypes.c_double
+        L.orc_weno_parts.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.orc_L.argtypes = [gp, ctypes.c_double, dp, dp, lp]
+        L.orc_step.argtypes = [gp, dp, ctypes.c_double, ctypes.c_int, dp, lp]
+        L.orc_totals.argtypes = [gp, dp, dp]
+        L.orc_hubble_prim.argtypes = [dp, ctypes.c_double, ctypes.c_long, dp, dp]
+        L.orc_jvp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
+        L.orc_riemann_conformal.argtypes = [ctypes.c_double] * 4 + [ctypes.c_long, dp, dp, dp]
+        for name in ("orc_vjp_L", "orc_vjp_step", "orc_step_store"):
+            if hasattr(L, name):
+                pass
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_grid(shape, h, c0, order=5, bc=(BC_PERIODIC,) * 3, eps=1e-6, hub=(10.0, 1.0, 0.5)):
+    """shape = (nx, ny, nz); h = (dx, dy, dz); c0 = centre of cell (0,0,0)."""
+    g = OrcGrid()
+    for a in range(3):
+        g.n[a] = int(shape[a])
+        g.h[a] = float(h[a])
+        g.c0[a] = float(c0[a])
+        g.bc[a] = int(bc[a])
+        g.hub[a] = float(hub[a])
+    g.order = int(order)
+    g.eps = float(eps)
+    return g
+
+
+def grid_from_spec(spec, order=None):
+    """Oracle grid from a workload spec produced by the input generators."""
+    return make_grid(spec["shape"], spec["h"], spec["c0"], order=order or spec.get("order", 5),
+                     bc=spec["bc"], eps=spec.get("eps", 1e-6),
+                     hub=spec.get("hub", (10.0, 1.0, 0.5)))
+
+
+def prim2con(prim):
+    prim = _f64(prim)
+    n = prim.size // 5
+    out = np.empty_like(prim)
+    lib().orc_prim2con(n, _dp(prim), _dp(out))
+    return out
+
+
+def con2prim(con, return_clamps=False):
+    con = _f64(con)
+    n = con.size // 5
+    out = np.empty_like(con)
+    cl = ctypes.c_long(0)
+    lib().orc_con2prim(n, _dp(con), _dp(out), ctypes.byref(cl))
+    return (out, cl.value) if return_clamps else out
+
+
+def flux(d, con):
+    con = _f64(con)
+    out = np.empty_like(con)
+    rc = lib().orc_flux(int(d), con.size // 5, _dp(con), _dp(out))
+    assert rc == 0
+    return out
+
+
+def weno(order, s, eps=1e-6, linear=False):
+    s = _f64(s)
+    assert s.size == order
+    return lib().orc_weno(int(order), _dp(s), float(eps), int(bool(linear)))
+
+
+def weno_parts(order, s):
+    s = _f64(s)
+    r = (order + 1) // 2
+    q = np.zeros(r)
+    b = np.zeros(r)
+    rc = lib().orc_weno_parts(int(order), _dp(s), _dp(q), _dp(b))
+    assert rc == 0
+    return q, b
+
+
+def apply_L(grid, u, t=0.0, return_clamps=False):
+    u = _f64(u)
+    out = np.empty_like(u)
+    cl = ctypes.c_long(0)
+    rc = lib().orc_L(ctypes.byref(grid), float(t), _dp(u), _dp(out), ctypes.byref(cl))
+    if rc != 0:
+        raise ValueError("orc_L rejected the grid description")
+    return (out, cl.value) if return_clamps else out
+
+
+def step(grid, u, dt, nsteps, t=0.0, return_clamps=False):
+    """Advance a copy of u by nsteps SSP-RK3 steps; returns (u, t[, clamps])."""
+    u = _f64(u).copy()
+    tt = ctypes.c_double(t)
+    cl = ctypes.c_long(0)
+    rc = lib().orc_step(ctypes.byref(grid), ctypes.byref(tt), float(dt), int(nsteps), _dp(u),
+                        ctypes.byref(cl))
+    if rc != 0:
+        raise ValueError("orc_step rejected its arguments")
+    return (u, tt.value, cl.value) if return_clamps else (u, tt.value)
+
+
+def totals(grid, u):
+    u = _f64(u)
+    out = np.zeros(5)
+    lib().orc_totals(ctypes.byref(grid), _dp(u), _dp(out))
+    return out
+
+
+def hubble_prim(hub, t, xyz):
+    xyz = _f64(xyz)
+    n = xyz.size // 3
+    out = np.empty((5, n))
+    h = _f64(hub)
+    lib().orc_hubble_prim(_dp(h), float(t), n, _dp(xyz), _dp(out))
+    return out
+
+
+def jvp_L(grid, u, v, t=0.0):
+    u = _f64(u)
+    v = _f64(v)
+    out = np.empty_like(u)
+    rc = lib().orc_jvp_L(ctypes.byref(grid), float(t), _dp(u), _dp(v), _dp(out))
+    assert rc == 0
+    return out
+
+
+def riemann_conformal(eL, nL, eR, nR, xi):
+    xi = _f64(xi)
+    out = np.empty((5, xi.size))
+    star = np.zeros(6)
+    rc = lib().orc_riemann_conformal(float(eL), float(nL), float(eR), float(nR), xi.size, _dp(xi),
+                                     _dp(out), _dp(star))
+    if rc != 0:
+        raise ValueError("riemann_conformal expects eL > eR > 0")
+    keys = ("e_star", "v_star", "n_left_star", "n_right_star", "v_shock", "xi_tail")
+    return out, dict(zip(keys, star))

@@ -1,0 +1,542 @@
+// rh_oracle.cpp -- plain FP64 CPU oracle for 3+1D ideal relativistic hydrodynamics
+// discretised with finite-difference WENO5/WENO7 and third-order SSP Runge-Kutta.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference
+// that the GPU path is checked against.  Only the test suite, the smoke check and
+// the CPU-baseline leg of the benchmark may load it.  It shares no code, header,
+// table or helper with the GPU library, and it never calls into it.
+//
+// What it follows (Sikorski et al., "Relativistic hydrodynamics on graphics
+// processing units", arXiv:1604.03360):
+//   * Sec. 1, Eq. (1): conservation laws du/dt + sum_i d f_i(u)/dx_i = 0 for the
+//     energy, momentum and charge densities u = (E, Mx, My, Mz, N).
+//   * Sec. 1, Eq. (2): semi-discrete operator on a Cartesian grid,
+//     L(u) = sum_i (F_i(x - e_i/2) - F_i(x + e_i/2)) / |e_i|, where F_i at a half
+//     cell is read as the finite-difference WENO numerical flux (Sec. 1.2).
+//   * Sec. 1: the ODE is integrated by a third-order Runge-Kutta method, read as the
+//     Shu-Osher strong-stability-preserving variant.
+//   * Sec. 1.2: finite-difference WENO of fifth and seventh order (Jiang-Shu
+//     smoothness indicators, nonlinear weights, component-wise, global
+//     Lax-Friedrichs splitting with alpha = 1).
+// Readings where the paper is silent (equation of state p = e/3, closed-form
+// primitive recovery, floors, boundary conditions, epsilon = 1e-6) are listed with
+// the design notes of the repository.
+//
+// Everything is templated on the scalar type so that T = std::complex<double>
+// evaluates the same arithmetic in complex-step mode (directional derivatives for
+// the adjoint checks).  Branches compare real parts only.
+//
+// Parity status: every function here is pinned by CPU tests against closed forms,
+// definitions derived symbolically at test time, exact solutions or invariants.
+// The hand-written VJP is pinned against the complex-step JVP (dot-product test).
+
+#include <cmath>
+#include <complex>
+#include <vector>
+#include <cstring>
+#include <cstdint>
+#include <algorithm>
+
+using cplx = std::complex<double>;
+
+namespace {
+
+inline double re(double x) { return x; }
+inline double re(const cplx& x) { return x.real(); }
+
+// ---------------------------------------------------------------------------
+// Grid description (the oracle's own; mirrors nothing outside this file).
+// ---------------------------------------------------------------------------
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_HUBBLE = 2 };
+
+// Floors applied to the primitive recovery only (never to the stored state).
+const double E_FLOOR = 1e-12;      // below this energy density the cell is treated as at rest
+const double V_DELTA = 1e-12;      // momentum squared capped at (1 - V_DELTA) E^2
+
+}  // namespace
+
+extern "C" {
+
+struct orc_grid {
+    int n[3];          // cells along x, y, z
+    double h[3];       // cell widths dx, dy, dz
+    double c0[3];      // centre of cell (0,0,0)
+    int order;         // 5 (WENO5) or 7 (WENO7)
+    int bc[3];         // per axis: 0 periodic, 1 outflow (zero gradient), 2 analytic Hubble flow
+    double eps;        // WENO epsilon
+    double hub[3];     // Hubble flow: t0, e0, n0
+};
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Equation of state and the state <-> primitive maps (Sec. 1, Eq. (1) variables)
+// Conformal EOS p = e/3.  Conserved: E = T^00, M_i = T^0i, N = n gamma.
+// ---------------------------------------------------------------------------
+template <class T>
+void prim2con(const T pr[5], T u[5]) {
+    // pr = (e, vx, vy, vz, n)
+    T e = pr[0], vx = pr[1], vy = pr[2], vz = pr[3], n = pr[4];
+    T p = e / 3.0;
+    T v2 = vx * vx + vy * vy + vz * vz;
+    T g2 = 1.0 / (1.0 - v2);
+    T w = e + p;
+    u[0] = w * g2 - p;
+    u[1] = w * g2 * vx;
+    u[2] = w * g2 * vy;
+    u[3] = w * g2 * vz;
+    u[4] = n * std::sqrt(g2);
+}
+
+// Closed-form inversion for p = e/3: with M^2 = |M|^2 and D = sqrt(4E^2 - 3M^2),
+// v = 3 M / (2E + D), p = (E^2 - M^2) / (E + D), n = N sqrt(1 - v^2).
+// Returns the velocity and pressure; *clamped is incremented when a floor acts.
+template <class T>
+void con2prim(const T u[5], T v[3], T& p, T& nden, long* clamped) {
+    T E = u[0], Mx = u[1], My = u[2], Mz = u[3], N = u[4];
+    if (re(E) < E_FLOOR) {
+        v[0] = v[1] = v[2] = T(0.0);
+        p = (re(E) > 0.0 ? E : T(0.0)) / 3.0;
+        nden = N;
+        if (clamped) ++*clamped;
+        return;
+    }
+    T M2 = Mx * Mx + My * My + Mz * Mz;
+    T cap = (1.0 - V_DELTA) * E * E;
+    if (re(M2) > re(cap)) {
+        T s = std::sqrt(cap / M2);
+        Mx = Mx * s; My = My * s; Mz = Mz * s;
+        M2 = cap;
+        if (clamped) ++*clamped;
+    }
+    T D = std::sqrt(4.0 * E * E - 3.0 * M2);
+    T k = 3.0 / (2.0 * E + D);
+    v[0] = k * Mx;
+    v[1] = k * My;
+    v[2] = k * Mz;
+    p = (E * E - M2) / (E + D);
+    nden = N * std::sqrt(1.0 - k * k * M2);
+}
+
+// Physical flux along axis d of Eq. (1): F_d = (M_d, M_x v_d + p delta_xd,
+// M_y v_d + p delta_yd, M_z v_d + p delta_zd, N v_d).
+template <class T>
+void flux(int d, const T u[5], const T v[3], T p, T f[5]) {
+    f[0] = u[1 + d];
+    f[1] = u[1] * v[d] + (d == 0 ? p : T(0.0));
+    f[2] = u[2] * v[d] + (d == 1 ? p : T(0.0));
+    f[3] = u[3] * v[d] + (d == 2 ? p : T(0.0));
+    f[4] = u[4] * v[d];
+}
+
+// ---------------------------------------------------------------------------
+// WENO reconstruction (Sec. 1.2).  Finite-difference form: the point values f_j
+// are treated as cell averages of a function h whose value at x_{i+1/2} is the
+// numerical flux.  s[0 .. 2r-2] holds f_{i-r+1} .. f_{i+r-1}; the result is the
+// left-biased reconstruction at i+1/2.
+// Candidate interpolants q_k, linear weights d_k and smoothness indicators beta_k
+// follow Jiang & Shu; beta_k = sum_{l=1}^{r-1} int_{cell} (d^l p_k / dx^l)^2 dx
+// with dx = 1 (written out as integer quadratic forms).
+// ---------------------------------------------------------------------------
+template <class T>
+void weno5_parts(const T s[5], T q[3], T b[3]) {
+    const T &fm2 = s[0], &fm1 = s[1], &f0 = s[2], &fp1 = s[3], &fp2 = s[4];
+    q[0] = (2.0 * fm2 - 7.0 * fm1 + 11.0 * f0) / 6.0;
+    q[1] = (-fm1 + 5.0 * f0 + 2.0 * fp1) / 6.0;
+    q[2] = (2.0 * f0 + 5.0 * fp1 - fp2) / 6.0;
+    T a0 = fm2 - 2.0 * fm1 + f0, c0 = fm2 - 4.0 * fm1 + 3.0 * f0;
+    T a1 = fm1 - 2.0 * f0 + fp1, c1 = fm1 - fp1;
+    T a2 = f0 - 2.0 * fp1 + fp2, c2 = 3.0 * f0 - 4.0 * fp1 + fp2;
+    b[0] = 13.0 / 12.0 * a0 * a0 + 0.25 * c0 * c0;
+    b[1] = 13.0 / 12.0 * a1 * a1 + 0.25 * c1 * c1;
+    b[2] = 13.0 / 12.0 * a2 * a2 + 0.25 * c2 * c2;
+}
+
+template <class T>
+void weno7_parts(const T s[7], T q[4], T b[4]) {
+    const T &m3 = s[0], &m2 = s[1], &m1 = s[2], &z0 = s[3], &p1 = s[4], &p2 = s[5], &p3 = s[6];
+    q[0] = (-3.0 * m3 + 13.0 * m2 - 23.0 * m1 + 25.0 * z0) / 12.0;
+    q[1] = (m2 - 5.0 * m1 + 13.0 * z0 + 3.0 * p1) / 12.0;
+    q[2] = (-m1 + 7.0 * z0 + 7.0 * p1 - p2) / 12.0;
+    q[3] = (3.0 * z0 + 13.0 * p1 - 5.0 * p2 + p3) / 12.0;
+    b[0] = (m3 * (547.0 * m3 - 3882.0 * m2 + 4642.0 * m1 - 1854.0 * z0)
+          + m2 * (7043.0 * m2 - 17246.0 * m1 + 7042.0 * z0)
+          + m1 * (11003.0 * m1 - 9402.0 * z0)
+          + 2107.0 * z0 * z0) / 240.0;
+    b[1] = (m2 * (267.0 * m2 - 1642.0 * m1 + 1602.0 * z0 - 494.0 * p1)
+          + m1 * (2843.0 * m1 - 5966.0 * z0 + 1922.0 * p1)
+          + z0 * (3443.0 * z0 - 2522.0 * p1)
+          + 547.0 * p1 * p1) / 240.0;
+    b[2] = (m1 * (547.0 * m1 - 2522.0 * z0 + 1922.0 * p1 - 494.0 * p2)
+          + z0 * (3443.0 * z0 - 5966.0 * p1 + 1602.0 * p2)
+          + p1 * (2843.0 * p1 - 1642.0 * p2)
+          + 267.0 * p2 * p2) / 240.0;
+    b[3] = (z0 * (2107.0 * z0 - 9402.0 * p1 + 7042.0 * p2 - 1854.0 * p3)
+          + p1 * (11003.0 * p1 - 17246.0 * p2 + 4642.0 * p3)
+          + p2 * (7043.0 * p2 - 3882.0 * p3)
+          + 547.0 * p3 * p3) / 240.0;
+}
+
+const double D5[3] = {1.0 / 10.0, 6.0 / 10.0, 3.0 / 10.0};
+const double D7[4] = {1.0 / 35.0, 12.0 / 35.0, 18.0 / 35.0, 4.0 / 35.0};
+
+// Nonlinear weights alpha_k = d_k / (eps + beta_k)^2, omega_k = alpha_k / sum(alpha).
+// linear != 0 replaces omega by d (used only by tests of the linear scheme).
+template <class T>
+T weno(int order, const T* s, double eps, int linear) {
+    int r = order == 5 ? 3 : 4;
+    T q[4], b[4];
+    const double* d;
+    if (order == 5) { weno5_parts(s, q, b); d = D5; }
+    else            { weno7_parts(s, q, b); d = D7; }
+    if (linear) {
+        T acc = 0.0;
+        for (int k = 0; k < r; ++k) acc += d[k] * q[k];
+        return acc;
+    }
+    T alpha[4], sum = 0.0;
+    for (int k = 0; k < r; ++k) {
+        T g = eps + b[k];
+        alpha[k] = d[k] / (g * g);
+        sum += alpha[k];
+    }
+    T acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += (alpha[k] / sum) * q[k];
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Analytic Hubble-like flow: u^mu = x^mu / tau, tau = sqrt(t^2 - r^2),
+// e = e0 (t0/tau)^4, n = n0 (t0/tau)^3, v = x/t.
+// ---------------------------------------------------------------------------
+void hubble_prim(const double hub[3], double t, double x, double y, double z, double pr[5]) {
+    double tau = std::sqrt(t * t - (x * x + y * y + z * z));
+    double s = hub[0] / tau;
+    pr[0] = hub[1] * s * s * s * s;
+    pr[1] = x / t;
+    pr[2] = y / t;
+    pr[3] = z / t;
+    pr[4] = hub[2] * s * s * s;
+}
+
+inline size_t cidx(const orc_grid& g, int i, int j, int k) {
+    return (size_t)i + (size_t)g.n[0] * ((size_t)j + (size_t)g.n[1] * (size_t)k);
+}
+
+// State of cell m along axis d on the line through (i, j, k), m may lie in the
+// ghost region; ghosts follow the axis boundary condition.
+template <class T>
+void line_cell(const orc_grid& g, double t, const T* u, int d, int ijk[3], int m, T out[5]) {
+    int nd = g.n[d];
+    int c[3] = {ijk[0], ijk[1], ijk[2]};
+    if (m >= 0 && m < nd) {
+        c[d] = m;
+    } else if (g.bc[d] == BC_PERIODIC) {
+        c[d] = ((m % nd) + nd) % nd;
+    } else if (g.bc[d] == BC_OUTFLOW) {
+        c[d] = m < 0 ? 0 : nd - 1;
+    } else {  // analytic Hubble flow at the ghost centre
+        c[d] = m;
+        double x[3];
+        for (int a = 0; a < 3; ++a) x[a] = g.c0[a] + c[a] * g.h[a];
+        double pr[5], uc[5];
+        hubble_prim(g.hub, t, x[0], x[1], x[2], pr);
+        prim2con(pr, uc);
+        for (int f = 0; f < 5; ++f) out[f] = T(uc[f]);
+        return;
+    }
+    size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+    size_t id = cidx(g, c[0], c[1], c[2]);
+    for (int f = 0; f < 5; ++f) out[f] = u[f * ncell + id];
+}
+
+// Eq. (2): L(u) = sum_d (Fhat_d(i-1/2) - Fhat_d(i+1/2)) / h_d, directions in the
+// order x, y, z, accumulated into a zeroed array.
+template <class T>
+void apply_L(const orc_grid& g, double t, const T* u, T* L, long* clamps) {
+    const int r = g.order == 5 ? 3 : 4;
+    const int G = r;  // ghost cells per side
+    size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+    for (size_t q = 0; q < 5 * ncell; ++q) L[q] = T(0.0);
+    long clamp_total = 0;
+    for (int d = 0; d < 3; ++d) {
+        int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        int nd = g.n[d];
+        long nlines = (long)g.n[a1] * g.n[a2];
+#pragma omp parallel for schedule(static) reduction(+ : clamp_total)
+        for (long line = 0; line < nlines; ++line) {
+            int ijk[3];
+            ijk[d] = 0;
+            ijk[a1] = (int)(line % g.n[a1]);
+            ijk[a2] = (int)(line / g.n[a1]);
+            int len = nd + 2 * G;
+            std::vector<T> fp(5 * len), fm(5 * len), Fh(5 * (nd + 1));
+            for (int m = -G; m < nd + G; ++m) {
+                T uc[5], v[3], p, nden, f[5];
+                line_cell(g, t, u, d, ijk, m, uc);
+                long cl = 0;
+                con2prim(uc, v, p, nden, &cl);
+                if (m >= 0 && m < nd) clamp_total += cl;
+                flux(d, uc, v, p, f);
+                // global Lax-Friedrichs splitting, alpha = 1
+                for (int c = 0; c < 5; ++c) {
+                    fp[c * len + m + G] = 0.5 * (f[c] + uc[c]);
+                    fm[c * len + m + G] = 0.5 * (f[c] - uc[c]);
+                }
+            }
+            // interfaces i+1/2 for i = -1 .. nd-1 stored at Fh[i+1]
+            for (int i = -1; i < nd; ++i) {
+                for (int c = 0; c < 5; ++c) {
+                    T sp[7], sm[7];
+                    for (int o = 0; o < 2 * r - 1; ++o) {
+                        sp[o] = fp[c * len + (i - r + 1 + o) + G];   // f+_{i-r+1+o}
+                        sm[o] = fm[c * len + (i + r - o) + G];       // mirrored: f-_{i+r-o}
+                    }
+                    Fh[c * (nd + 1) + i + 1] = weno(g.order, sp, g.eps, 0) + weno(g.order, sm, g.eps, 0);
+                }
+            }
+            for (int i = 0; i < nd; ++i) {
+                int cc[3] = {ijk[0], ijk[1], ijk[2]};
+                cc[d] = i;
+                size_t id = cidx(g, cc[0], cc[1], cc[2]);
+                for (int c = 0; c < 5; ++c)
+                    L[c * ncell + id] += (Fh[c * (nd + 1) + i] - Fh[c * (nd + 1) + i + 1]) / g.h[d];
+            }
+        }
+    }
+    if (clamps) *clamps += clamp_total;
+}
+
+// Shu-Osher SSP-RK3 (Sec. 1, third-order Runge-Kutta), stage times t, t+dt, t+dt/2.
+void rk3_step(const orc_grid& g, double t, double dt, double* u, long* clamps) {
+    size_t N = 5 * (size_t)g.n[0] * g.n[1] * g.n[2];
+    std::vector<double> L(N), u1(N), u2(N);
+    apply_L(g, t, u, L.data(), clamps);
+    for (size_t q = 0; q < N; ++q) u1[q] = u[q] + dt * L[q];
+    apply_L(g, t + dt, u1.data(), L.data(), clamps);
+    for (size_t q = 0; q < N; ++q) u2[q] = 0.75 * u[q] + 0.25 * (u1[q] + dt * L[q]);
+    apply_L(g, t + 0.5 * dt, u2.data(), L.data(), clamps);
+    for (size_t q = 0; q < N; ++q) u[q] = (1.0 / 3.0) * u[q] + (2.0 / 3.0) * (u2[q] + dt * L[q]);
+}
+
+bool grid_ok(const orc_grid* g) {
+    if (!g) return false;
+    if (g->order != 5 && g->order != 7) return false;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1 || !(g->h[a] > 0.0)) return false;
+        if (g->bc[a] < 0 || g->bc[a] > 2) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Primitive (e, vx, vy, vz, n) -> conserved (E, Mx, My, Mz, N), SoA [5][n].
+int orc_prim2con(long n, const double* prim, double* con) {
+    for (long i = 0; i < n; ++i) {
+        double pr[5], u[5];
+        for (int f = 0; f < 5; ++f) pr[f] = prim[f * n + i];
+        prim2con(pr, u);
+        for (int f = 0; f < 5; ++f) con[f * n + i] = u[f];
+    }
+    return 0;
+}
+
+// Conserved -> primitive (e, vx, vy, vz, n) with floors; SoA [5][n].
+int orc_con2prim(long n, const double* con, double* prim, long* clamps) {
+    long cl = 0;
+    for (long i = 0; i < n; ++i) {
+        double u[5], v[3], p, nd;
+        for (int f = 0; f < 5; ++f) u[f] = con[f * n + i];
+        con2prim(u, v, p, nd, &cl);
+        prim[0 * n + i] = 3.0 * p;
+        prim[1 * n + i] = v[0];
+        prim[2 * n + i] = v[1];
+        prim[3 * n + i] = v[2];
+        prim[4 * n + i] = nd;
+    }
+    if (clamps) *clamps = cl;
+    return 0;
+}
+
+// Physical flux along axis d for n states (SoA [5][n]).
+int orc_flux(int d, long n, const double* con, double* f_out) {
+    if (d < 0 || d > 2) return -1;
+    for (long i = 0; i < n; ++i) {
+        double u[5], v[3], p, nd, f[5];
+        for (int c = 0; c < 5; ++c) u[c] = con[c * n + i];
+        con2prim(u, v, p, nd, (long*)nullptr);
+        flux(d, u, v, p, f);
+        for (int c = 0; c < 5; ++c) f_out[c * n + i] = f[c];
+    }
+    return 0;
+}
+
+// One WENO reconstruction from 2r-1 values (left-biased, at i+1/2).
+double orc_weno(int order, const double* s, double eps, int linear) {
+    return weno(order, s, eps, linear);
+}
+
+// Candidate values q_k and smoothness indicators beta_k of one stencil.
+int orc_weno_parts(int order, const double* s, double* q, double* b) {
+    if (order == 5) weno5_parts(s, q, b);
+    else if (order == 7) weno7_parts(s, q, b);
+    else return -1;
+    return 0;
+}
+
+// L(u) at time t (t only matters for analytic boundaries).  u, L: [5][nz][ny][nx].
+int orc_L(const orc_grid* g, double t, const double* u, double* L, long* clamps) {
+    if (!grid_ok(g)) return -1;
+    apply_L(*g, t, u, L, clamps);
+    return 0;
+}
+
+// n SSP-RK3 steps of size dt, in place; *t is advanced.
+int orc_step(const orc_grid* g, double* t, double dt, int nsteps, double* u, long* clamps) {
+    if (!grid_ok(g) || !(dt > 0.0) || nsteps < 0) return -1;
+    for (int s = 0; s < nsteps; ++s) {
+        rk3_step(*g, *t, dt, u, clamps);
+        *t += dt;
+    }
+    return 0;
+}
+
+// Compensated (Kahan) FP64 sums of the five conserved fields over all cells.
+int orc_totals(const orc_grid* g, const double* u, double out[5]) {
+    if (!grid_ok(g)) return -1;
+    size_t ncell = (size_t)g->n[0] * g->n[1] * g->n[2];
+    for (int f = 0; f < 5; ++f) {
+        double s = 0.0, c = 0.0;
+        for (size_t i = 0; i < ncell; ++i) {
+            double y = u[f * ncell + i] - c;
+            double tt = s + y;
+            c = (tt - s) - y;
+            s = tt;
+        }
+        out[f] = s;
+    }
+    return 0;
+}
+
+// Analytic Hubble-like flow primitives at n points xyz[3][n] at time t.
+int orc_hubble_prim(const double hub[3], double t, long n, const double* xyz, double* prim) {
+    for (long i = 0; i < n; ++i) {
+        double pr[5];
+        hubble_prim(hub, t, xyz[i], xyz[n + i], xyz[2 * n + i], pr);
+        for (int f = 0; f < 5; ++f) prim[f * n + i] = pr[f];
+    }
+    return 0;
+}
+
+// Directional derivative J(u) v of L at u by the complex step:
+// Jv = Im L(u + i h v) / h with h = 1e-30 (no subtractive cancellation).
+int orc_jvp_L(const orc_grid* g, double t, const double* u, const double* v, double* jv) {
+    if (!grid_ok(g)) return -1;
+    const double h = 1e-30;
+    size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
+    std::vector<cplx> uc(N), Lc(N);
+    for (size_t q = 0; q < N; ++q) uc[q] = cplx(u[q], h * v[q]);
+    apply_L(*g, t, uc.data(), Lc.data(), (long*)nullptr);
+    for (size_t q = 0; q < N; ++q) jv[q] = Lc[q].imag() / h;
+    return 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Exact Riemann solution for the conformal fluid (p = e/3) with both initial
+// states at rest and e_L > e_R: a left-moving rarefaction, a contact and a
+// right-moving shock.  This is the analytic reference of the shock-tube test
+// (Sec. 3, Fig. 1).
+//   * Rarefaction: the Riemann invariant artanh(v) + (sqrt(3)/4) ln e is constant
+//     across the fan; inside it xi = (v - c_s) / (1 - v c_s), c_s = 1/sqrt(3);
+//     the flow is isentropic, so n / e^(3/4) is constant.
+//   * Shock: in the shock frame the normal velocities obey v_a v_b = 1/3 and the
+//     energy densities e_b / e_a = (9 v_a^2 - 1) / (3 (1 - v_a^2)); the charge
+//     flux n gamma v is continuous.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RiemannStar {
+    double e_star, v_star, n_left_star, n_right_star, v_shock, xi_tail;
+};
+
+double shock_post_velocity(double vs) {
+    // lab-frame velocity behind a shock moving at vs into fluid at rest
+    double vb = 1.0 / (3.0 * vs);
+    return (vs - vb) / (1.0 - vs * vb);
+}
+double shock_energy_ratio(double vs) { return (9.0 * vs * vs - 1.0) / (3.0 * (1.0 - vs * vs)); }
+
+RiemannStar riemann_star(double eL, double nL, double eR, double nR) {
+    const double sq3 = std::sqrt(3.0);
+    // residual in the shock speed: velocity behind the shock minus velocity at the
+    // same energy density on the rarefaction branch
+    auto resid = [&](double vs) {
+        double es = eR * shock_energy_ratio(vs);
+        double v_rare = std::tanh(0.25 * sq3 * std::log(eL / es));
+        return shock_post_velocity(vs) - v_rare;
+    };
+    double lo = 1.0 / sq3, hi = 1.0;
+    // resid(lo) < 0 (no shock, rarefaction still accelerates), resid(hi) > 0
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (resid(mid) < 0.0) lo = mid; else hi = mid;
+    }
+    RiemannStar s;
+    s.v_shock = 0.5 * (lo + hi);
+    s.e_star = eR * shock_energy_ratio(s.v_shock);
+    s.v_star = shock_post_velocity(s.v_shock);
+    s.n_left_star = nL * std::pow(s.e_star / eL, 0.75);
+    // charge flux continuity in the shock frame: n_a gamma_a v_a = n_b gamma_b v_b
+    double va = s.v_shock, vb = 1.0 / (3.0 * s.v_shock);
+    double ga = 1.0 / std::sqrt(1.0 - va * va), gb = 1.0 / std::sqrt(1.0 - vb * vb);
+    s.n_right_star = nR * ga * va / (gb * vb);
+    double cs = 1.0 / sq3;
+    s.xi_tail = (s.v_star - cs) / (1.0 - s.v_star * cs);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+// prim_out[5][n] = (e, v, 0, 0, n) at similarity coordinates xi[i] = x/t.
+// star_out (6 doubles, may be null): e*, v*, n* left of contact, n* right of
+// contact, shock speed, rarefaction tail speed.
+int orc_riemann_conformal(double eL, double nL, double eR, double nR, long n, const double* xi,
+                          double* prim_out, double* star_out) {
+    if (!(eL > eR) || !(eR > 0.0)) return -1;
+    RiemannStar s = riemann_star(eL, nL, eR, nR);
+    const double cs = 1.0 / std::sqrt(3.0);
+    for (long i = 0; i < n; ++i) {
+        double x = xi[i], e, v, nn;
+        if (x < -cs) { e = eL; v = 0.0; nn = nL; }
+        else if (x < s.xi_tail) {
+            v = (x + cs) / (1.0 + x * cs);
+            e = eL * std::exp(-(4.0 / std::sqrt(3.0)) * std::atanh(v));
+            nn = nL * std::pow(e / eL, 0.75);
+        }
+        else if (x < s.v_star) { e = s.e_star; v = s.v_star; nn = s.n_left_star; }
+        else if (x < s.v_shock) { e = s.e_star; v = s.v_star; nn = s.n_right_star; }
+        else { e = eR; v = 0.0; nn = nR; }
+        prim_out[0 * n + i] = e;
+        prim_out[1 * n + i] = v;
+        prim_out[2 * n + i] = 0.0;
+        prim_out[3 * n + i] = 0.0;
+        prim_out[4 * n + i] = nn;
+    }
+    if (star_out) {
+        star_out[0] = s.e_star; star_out[1] = s.v_star; star_out[2] = s.n_left_star;
+        star_out[3] = s.n_right_star; star_out[4] = s.v_shock; star_out[5] = s.xi_tail;
+    }
+    return 0;
+}
+
+}  // extern "C"
