@@ -1,0 +1,202 @@
+"""Benchmark of the WENO5 / SSP-RK3 hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 3+1D ellipsoidal Gaussian energy blob at rest on a periodic
+256^3 grid (dx = 0.1, dt = 0.04, WENO5, conformal EOS), the synthetic stand-in
+for the paper's ellipsoidal-flow run.  One step is one full SSP-RK3 step
+(three evaluations of L, nine directional sweeps).  The state is resident in
+HBM before the timed region; K steps are timed between stream synchronisations.
+
+Prints ONE JSON line.  `value` is FP32 cell-updates/s (storage, stencil and
+Runge-Kutta in FP32, primitive recovery in FP64); the FP64 run is reported
+beside it.  The roofline block is for the dominant sweep kernel, timed live
+with HIP events on the library's stream; the CPU baseline is the FP64 oracle on
+the host cores over a bounded sample (whole-grid steps of the same workload).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WENO5-RK3 cell-updates/s @256^3 FP32 vs FP64, %HBM peak; adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0
+# MI355X vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s (packed), FP64 78.6 TFLOP/s
+ALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+
+# Algorithmic FP operations per cell for one directional sweep (textbook formulas,
+# add/mul/div/sqrt = 1): 10 WENO reconstructions (WENO5: 69 each; WENO7: 194 each)
+# + 5 face sums + flux and Lax-Friedrichs split (25) + flux difference (10) + one
+# third of the primitive recovery (20 / 3) + accumulation of L (5).
+WENO_FLOPS = {5: 69, 7: 194}
+
+
+def sweep_flops_per_cell(order):
+    return 10 * WENO_FLOPS[order] + 5 + 25 + 10 + 20.0 / 3.0 + 5
+
+
+# Algorithmic HBM bytes per cell for each sweep class (values per cell x size):
+# x sweep reads u (5) and writes L (5); y sweep reads u, L and writes L (15);
+# z sweep reads u, L, u^n and writes the new state (20; 15 in stage 1).
+SWEEP_VALUES = {"sweep_x": 10.0, "sweep_y": 15.0, "sweep_z": (15.0 + 20.0 + 20.0) / 3.0}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for name in ("rh_device.hpp", "rh_internal.hpp", "rh_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1604_03360_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, precision):
+    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_blob256.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(precision, {}).get(kernel)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def run_gpu(spec, precision, steps, warmup):
+    import torch
+    from paper_1604_03360_amd import rh
+    prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    h.set_primitive(spec["prim"])
+    dt = spec["dt"]
+    if warmup:
+        h.step(dt, warmup)
+    stream = torch.cuda.current_stream()
+    stream.synchronize()
+    rh.rh_set_timing(h.plan, 1)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    h.step(dt, steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t0.elapsed_time(t1)
+    ktimes = rh.rh_kernel_times(h.plan)
+    rh.rh_set_timing(h.plan, 0)
+    tot, cnt = h.totals()
+    h.close()
+    del h
+    torch.cuda.empty_cache()
+    ncell = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
+    return {"ms_per_step": ms_total / steps, "wall_s": wall, "value": ncell * steps / (ms_total * 1e-3),
+            "kernels": ktimes, "totals": tot, "counters": cnt}
+
+
+def roofline(run, precision, order, ncell):
+    elem = 4 if precision == "fp32" else 8
+    kern = {k: v for k, v in run["kernels"].items() if k.startswith("sweep")}
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, launches = kern[dom]
+    avg_s = ms / launches * 1e-3
+    flops = sweep_flops_per_cell(order) * ncell
+    achieved = flops / avg_s / 1e12
+    peak = ALU_PEAK_TFLOPS[precision]
+    alg_bytes = SWEEP_VALUES[dom] * elem * ncell
+    traffic = load_traffic(dom, precision)
+    return dom, {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4), "traffic": traffic,
+        "kernel": dom, "avg_launch_ms": round(ms / launches, 4),
+        "flops_per_cell": sweep_flops_per_cell(order),
+    }, {
+        "kernel": dom, "alg_bytes_per_launch": alg_bytes,
+        "achieved_GBps": round(alg_bytes / avg_s / 1e9, 1), "peak_GBps": HBM_PEAK_GBS,
+        "frac": round(alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+
+def cpu_baseline(spec, nsteps):
+    import oracle
+    oracle.build()
+    g = oracle.grid_from_spec(spec)
+    u = oracle.prim2con(spec["prim"])
+    t0 = time.perf_counter()
+    oracle.step(g, u, spec["dt"], nsteps)
+    el = time.perf_counter() - t0
+    ncell = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
+    return {"value": ncell * nsteps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d whole-grid SSP-RK3 step(s) of the same 256^3 WENO5 blob, FP64, %.1f s"
+                      % (nsteps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--scheme", type=int, default=5, choices=(5, 7))
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the path has no multi-GPU mode); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1604_03360_amd import inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spec = inputs.blob(n=args.n, order=args.scheme)
+    ncell = args.n ** 3
+    print("bench: blob %d^3 WENO%d, %d warmup + %d timed steps" % (args.n, args.scheme, args.warmup,
+                                                                  args.steps), file=sys.stderr, flush=True)
+    r32 = run_gpu(spec, "fp32", args.steps, args.warmup)
+    print("bench: fp32 %.4g cell-updates/s (%.3f ms/step)" % (r32["value"], r32["ms_per_step"]),
+          file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(spec, "fp64", args.steps, args.warmup)
+        print("bench: fp64 %.4g cell-updates/s (%.3f ms/step)" % (r64["value"], r64["ms_per_step"]),
+              file=sys.stderr, flush=True)
+    dom, roof, hbm = roofline(r32, "fp32", args.scheme, ncell)
+    out = {
+        "metric": METRIC, "value": r32["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ellipsoidal Gaussian blob at rest, %d^3 periodic, dx=0.1, dt=0.04, "
+                               "WENO%d + global Lax-Friedrichs, SSP-RK3, p=e/3" % (args.n, args.scheme),
+                   "grid": [args.n] * 3, "precision": "FP32 storage/stencil/RK, FP64 primitive recovery",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "hbm": hbm,
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in r32["kernels"].items()},
+        "counters": r32["counters"],
+    }
+    if r64 is not None:
+        _, roof64, hbm64 = roofline(r64, "fp64", args.scheme, ncell)
+        out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                       "fp32_over_fp64": r32["value"] / r64["value"], "roofline": roof64, "hbm": hbm64,
+                       "kernels_ms_per_step": {k: v[0] / args.steps for k, v in r64["kernels"].items()}}
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

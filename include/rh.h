@@ -1,0 +1,170 @@
+/*
+ * rh.h -- C ABI of the MI355X (gfx950) relativistic-hydrodynamics hot path.
+ *
+ * The library advances the 3+1D ideal relativistic hydrodynamics equations in
+ * conservation form (Sikorski et al., arXiv:1604.03360, Sec. 1, Eq. (1)) for the
+ * conserved densities u = (E, Mx, My, Mz, N) on a Cartesian grid.  Each right-
+ * hand-side evaluation is the semi-discrete operator L(u) of Eq. (2), with the
+ * half-cell fluxes given by finite-difference WENO5 or WENO7 reconstruction
+ * (Sec. 1.2) of globally Lax-Friedrichs-split physical fluxes; the ODE is
+ * integrated with the third-order strong-stability-preserving Runge-Kutta
+ * method (Sec. 1).  The equation of state is conformal, p = e/3, and N is a
+ * passive conserved charge.
+ *
+ * Conventions shared by every call:
+ *   - Fields are structure-of-arrays, [5][nz][ny][nx] with x fastest, in the
+ *     order E, Mx, My, Mz, N (conserved) or e, vx, vy, vz, n (primitive).
+ *   - Device pointers are HIP device addresses on the current device; the
+ *     caller owns every buffer passed in (the library never frees them).
+ *   - All work is enqueued asynchronously on the stream given to rh_bind
+ *     (a hipStream_t passed as void*; NULL means the legacy default stream).
+ *     Only rh_totals, rh_kernel_times and the *_fields calls with a host
+ *     result synchronise that stream.
+ *   - Every call returns RH_OK (0) or a negative rh_status; the message of
+ *     the last failure on the calling thread is available from rh_last_error.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef RH_H
+#define RH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int rh_status;
+#define RH_OK         0
+#define RH_E_INVAL   -1  /* invalid argument: bad sizes, widths, scheme, precision, boundary */
+#define RH_E_NOMEM   -2  /* a library-owned device allocation failed */
+#define RH_E_HIP     -3  /* a HIP runtime call or kernel launch failed (message has details) */
+#define RH_E_STATE   -4  /* call out of order, e.g. stepping a plan with no bound buffers */
+#define RH_E_NOTSUP  -5  /* valid request that this build does not support */
+#define RH_E_PHYS    -6  /* strict mode: a primitive-recovery floor acted or a value is not finite */
+
+/* Arithmetic of a plan.  RH_PREC_FP64: storage, stencil and Runge-Kutta in FP64.
+ * RH_PREC_FP32: storage, stencil and Runge-Kutta in FP32, with the primitive
+ * recovery (the velocity root solve) and the conservation totals in FP64. */
+#define RH_PREC_FP64 0
+#define RH_PREC_FP32 1
+
+/* Boundary condition of one axis.  PERIODIC wraps; OUTFLOW copies the edge cell
+ * into the ghost cells (zero gradient); HUBBLE fills ghost cells with the
+ * analytic Hubble-like flow u^mu = x^mu/tau, tau = sqrt(t^2 - r^2),
+ * e = e0 (t0/tau)^4, n = n0 (t0/tau)^3 at the Runge-Kutta stage time (Sec. 3).
+ * An axis with one cell contributes nothing to L whatever its condition. */
+#define RH_BC_PERIODIC 0
+#define RH_BC_OUTFLOW  1
+#define RH_BC_HUBBLE   2
+
+/* Field kinds for rh_set_fields / rh_get_fields. */
+#define RH_FIELDS_CONSERVED 0  /* E, Mx, My, Mz, N */
+#define RH_FIELDS_PRIMITIVE 1  /* e, vx, vy, vz, n */
+
+/* Kernel classes reported by rh_kernel_times. */
+#define RH_KERNEL_SWEEP_X 0   /* x-direction WENO sweep */
+#define RH_KERNEL_SWEEP_Y 1   /* y-direction WENO sweep */
+#define RH_KERNEL_SWEEP_Z 2   /* z-direction WENO sweep */
+#define RH_KERNEL_OTHER   3   /* combine, conversion and reduction kernels */
+#define RH_KERNEL_CLASSES 4
+
+typedef struct rh_grid_desc {
+    int nx, ny, nz;          /* cells per axis, each >= 1 */
+    double dx, dy, dz;       /* cell widths, > 0 */
+    double x0, y0, z0;       /* position of the centre of cell (0,0,0) (used by HUBBLE) */
+    int scheme;              /* 5 (WENO5, 3 ghost cells) or 7 (WENO7, 4 ghost cells) */
+    int precision;           /* RH_PREC_FP64 or RH_PREC_FP32 */
+    int bc[3];               /* RH_BC_* for the x, y and z axes */
+    double weno_eps;         /* epsilon of the nonlinear weights; 0 selects 1e-6 */
+    double hubble_t0;        /* HUBBLE only: reference time t0 */
+    double hubble_e0;        /* HUBBLE only: e at tau = t0 */
+    double hubble_n0;        /* HUBBLE only: n at tau = t0 */
+    int strict;              /* nonzero: rh_totals reports RH_E_PHYS when a floor acted */
+} rh_grid_desc;
+
+typedef struct rh_plan rh_plan;
+
+/* Message of the last failing call on this thread ("" if none).  Owned by the
+ * library; valid until the next call on the same thread. */
+const char* rh_last_error(void);
+
+/* Library version string (static storage). */
+const char* rh_version(void);
+
+/* Create a plan for one grid (Eq. (2) on a Cartesian grid).  Validates the
+ * description and allocates only small plan-owned device memory (counters and
+ * reduction partials).  *out receives the plan; it is NULL on failure.
+ * Errors: RH_E_INVAL (bad description), RH_E_NOMEM, RH_E_HIP. */
+rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* desc);
+
+/* Release a plan and its own device memory; never touches caller buffers.
+ * The caller must ensure no work of this plan is still running. NULL is ignored. */
+void rh_plan_destroy(rh_plan* plan);
+
+/* Bytes of one state: 5 * nx * ny * nz * (8 for FP64, 4 for FP32). */
+size_t rh_state_bytes(const rh_plan* plan);
+
+/* Bytes of the workspace the caller must provide to rh_bind: the two
+ * intermediate Runge-Kutta stage states and the L accumulator (3 states). */
+size_t rh_workspace_bytes(const rh_plan* plan);
+
+/* Bind caller-owned device buffers and a stream.  state: rh_state_bytes bytes,
+ * the solution u^n, updated in place by rh_step.  workspace: rh_workspace_bytes
+ * bytes, contents scratch.  Both must be 16-byte aligned and stay valid while
+ * work of this plan is pending on the stream.  Rebinding is allowed at any
+ * time between calls.  Errors: RH_E_INVAL (NULL or misaligned buffer). */
+rh_status rh_bind(rh_plan* plan, void* state, void* workspace, void* stream);
+
+/* Write the bound state from FP64 device fields src[5][nz][ny][nx] of the given
+ * kind.  PRIMITIVE input is converted to conserved variables in FP64
+ * (E = (e+p) g^2 - p, M = (e+p) g^2 v, N = n g, g = 1/sqrt(1-v^2)) and then
+ * rounded to the plan precision.  Asynchronous.
+ * Errors: RH_E_STATE (unbound), RH_E_INVAL (kind). */
+rh_status rh_set_fields(rh_plan* plan, const double* src, int kind);
+
+/* Read the bound state into FP64 device fields dst[5][nz][ny][nx].  PRIMITIVE
+ * output runs the FP64 closed-form primitive recovery for p = e/3 (the same
+ * recovery as the sweeps).  Asynchronous. Errors: RH_E_STATE, RH_E_INVAL. */
+rh_status rh_get_fields(rh_plan* plan, double* dst, int kind);
+
+/* Evaluate L(u) of Eq. (2) for the bound state at physical time t (t matters
+ * only for HUBBLE boundaries) into the caller's device buffer L_out, which has
+ * the plan precision and layout [5][nz][ny][nx] and must not alias the bound
+ * buffers.  Directions are accumulated in the order x, y, z.  Asynchronous.
+ * Errors: RH_E_STATE (unbound), RH_E_INVAL (NULL or aliasing L_out). */
+rh_status rh_apply_L(rh_plan* plan, double t, void* L_out);
+
+/* Advance the bound state by n_steps steps of the Shu-Osher SSP-RK3 method
+ * (Sec. 1): u1 = u + dt L(u, t); u2 = 3/4 u + 1/4 (u1 + dt L(u1, t+dt));
+ * u <- 1/3 u + 2/3 (u2 + dt L(u2, t+dt/2)).  The combine of each stage is
+ * fused into its last directional sweep.  *t_inout is the physical time of the
+ * state (used for HUBBLE boundaries) and is advanced by n_steps*dt on return
+ * (host-side; the device work is asynchronous).  n_steps == 0 is a no-op.
+ * Errors: RH_E_INVAL (dt <= 0, n_steps < 0, NULL t_inout), RH_E_STATE, RH_E_HIP. */
+rh_status rh_step(rh_plan* plan, double dt, int n_steps, double* t_inout);
+
+/* Conservation diagnostics of the bound state: out[0..4] = FP64 sums of E, Mx,
+ * My, Mz and N over all cells (deterministic fixed-order two-pass reduction,
+ * not multiplied by the cell volume).  counters (may be NULL) receives
+ * [0] = primitive recoveries that hit a floor since the plan was created or
+ * last reset, [1] = cells with a non-finite conserved value.  Synchronises the
+ * stream.  Errors: RH_E_STATE, RH_E_HIP, RH_E_PHYS (strict plans only). */
+rh_status rh_totals(rh_plan* plan, double out[5], long long counters[2]);
+
+/* Reset the floor counter reported by rh_totals to zero (asynchronous). */
+rh_status rh_reset_counters(rh_plan* plan);
+
+/* Enable (nonzero) or disable per-kernel timing with HIP events recorded on
+ * the bound stream around every launch.  Enabling clears earlier records. */
+rh_status rh_set_timing(rh_plan* plan, int enable);
+
+/* Per kernel class (RH_KERNEL_*): total milliseconds and number of launches
+ * recorded since timing was enabled.  ms_out and launches_out hold n entries
+ * (n <= RH_KERNEL_CLASSES).  Synchronises the stream. */
+rh_status rh_kernel_times(rh_plan* plan, double* ms_out, long long* launches_out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RH_H */

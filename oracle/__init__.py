@@ -66,11 +66,14 @@ def lib():
         L.orc_hubble_prim.argtypes = [dp, ctypes.c_double, ctypes.c_long, dp, dp]
         L.orc_jvp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
         L.orc_riemann_conformal.argtypes = [ctypes.c_double] * 4 + [ctypes.c_long, dp, dp, dp]
-        for name in ("orc_vjp_L", "orc_vjp_step", "orc_step_store"):
-            if hasattr(L, name):
-                pass
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use."""
+    return lib().orc_num_threads()
 
 
 def _dp(a):

@@ -138,7 +138,8 @@ void flux(int d, const T u[5], const T v[3], T p, T f[5]) {
 // left-biased reconstruction at i+1/2.
 // Candidate interpolants q_k, linear weights d_k and smoothness indicators beta_k
 // follow Jiang & Shu; beta_k = sum_{l=1}^{r-1} int_{cell} (d^l p_k / dx^l)^2 dx
-// with dx = 1 (written out as integer quadratic forms).
+// with dx = 1, written as squares of difference combinations (WENO5) or from
+// the derivative coefficients of the cubic candidate polynomial (WENO7).
 // ---------------------------------------------------------------------------
 template <class T>
 void weno5_parts(const T s[5], T q[3], T b[3]) {
@@ -161,22 +162,25 @@ void weno7_parts(const T s[7], T q[4], T b[4]) {
     q[1] = (m2 - 5.0 * m1 + 13.0 * z0 + 3.0 * p1) / 12.0;
     q[2] = (-m1 + 7.0 * z0 + 7.0 * p1 - p2) / 12.0;
     q[3] = (3.0 * z0 + 13.0 * p1 - 5.0 * p2 + p3) / 12.0;
-    b[0] = (m3 * (547.0 * m3 - 3882.0 * m2 + 4642.0 * m1 - 1854.0 * z0)
-          + m2 * (7043.0 * m2 - 17246.0 * m1 + 7042.0 * z0)
-          + m1 * (11003.0 * m1 - 9402.0 * z0)
-          + 2107.0 * z0 * z0) / 240.0;
-    b[1] = (m2 * (267.0 * m2 - 1642.0 * m1 + 1602.0 * z0 - 494.0 * p1)
-          + m1 * (2843.0 * m1 - 5966.0 * z0 + 1922.0 * p1)
-          + z0 * (3443.0 * z0 - 2522.0 * p1)
-          + 547.0 * p1 * p1) / 240.0;
-    b[2] = (m1 * (547.0 * m1 - 2522.0 * z0 + 1922.0 * p1 - 494.0 * p2)
-          + z0 * (3443.0 * z0 - 5966.0 * p1 + 1602.0 * p2)
-          + p1 * (2843.0 * p1 - 1642.0 * p2)
-          + 267.0 * p2 * p2) / 240.0;
-    b[3] = (z0 * (2107.0 * z0 - 9402.0 * p1 + 7042.0 * p2 - 1854.0 * p3)
-          + p1 * (11003.0 * p1 - 17246.0 * p2 + 4642.0 * p3)
-          + p2 * (7043.0 * p2 - 3882.0 * p3)
-          + 547.0 * p3 * p3) / 240.0;
+    // beta_k = int_cell (p')^2 + (p'')^2 + (p''')^2 for the cubic candidate
+    // p_k(x) = a0 + a1 x + a2 x^2 + a3 x^3 (x in cells from the centre of cell i):
+    // beta_k = a1^2 + a1 a3 / 2 + 13/3 a2^2 + 3129/80 a3^2.
+    T a1[4], a2[4], a3[4];
+    a1[0] = (-7.0 * m3 + 33.0 * m2 - 69.0 * m1 + 43.0 * z0) / 24.0;
+    a2[0] = (-m3 + 4.0 * m2 - 5.0 * m1 + 2.0 * z0) / 2.0;
+    a3[0] = (-m3 + 3.0 * m2 - 3.0 * m1 + z0) / 6.0;
+    a1[1] = (5.0 * m2 - 27.0 * m1 + 15.0 * z0 + 7.0 * p1) / 24.0;
+    a2[1] = (m1 - 2.0 * z0 + p1) / 2.0;
+    a3[1] = (-m2 + 3.0 * m1 - 3.0 * z0 + p1) / 6.0;
+    a1[2] = (-7.0 * m1 - 15.0 * z0 + 27.0 * p1 - 5.0 * p2) / 24.0;
+    a2[2] = (m1 - 2.0 * z0 + p1) / 2.0;
+    a3[2] = (-m1 + 3.0 * z0 - 3.0 * p1 + p2) / 6.0;
+    a1[3] = (-43.0 * z0 + 69.0 * p1 - 33.0 * p2 + 7.0 * p3) / 24.0;
+    a2[3] = (2.0 * z0 - 5.0 * p1 + 4.0 * p2 - p3) / 2.0;
+    a3[3] = (-z0 + 3.0 * p1 - 3.0 * p2 + p3) / 6.0;
+    for (int k = 0; k < 4; ++k)
+        b[k] = a1[k] * a1[k] + 0.5 * a1[k] * a3[k] + 13.0 / 3.0 * a2[k] * a2[k]
+             + 3129.0 / 80.0 * a3[k] * a3[k];
 }
 
 const double D5[3] = {1.0 / 10.0, 6.0 / 10.0, 3.0 / 10.0};
@@ -540,3 +544,15 @@ int orc_riemann_conformal(double eL, double nL, double eR, double nR, long n, co
 }
 
 }  // extern "C"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+extern "C" int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

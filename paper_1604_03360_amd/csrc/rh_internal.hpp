@@ -1,0 +1,55 @@
+// rh_internal.hpp -- host-side interface between the plan runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rh_device.hpp"
+
+namespace rh {
+
+// Epilogue of the last directional sweep of an evaluation of L:
+//   0: write L (accumulated over the directions done so far) to `lacc`;
+//   1..3: fuse the SSP-RK3 stage combine and write the new state to `uout`.
+enum { STAGE_WRITE_L = 0, STAGE_1 = 1, STAGE_2 = 2, STAGE_3 = 3 };
+
+template <class T>
+struct SweepArgs {
+    const T* us;        // stage input (stencil source)
+    const T* u0;        // u^n (stages 2 and 3 read it pointwise)
+    T* lacc;            // L accumulator: read unless `first`, written when stage == 0
+    T* uout;            // new state when stage > 0 (may alias u0: read pointwise first)
+    long long fstride;  // elements per field (nx*ny*nz)
+    int n[3];           // nx, ny, nz
+    int bc;             // boundary condition of the sweep axis
+    int first;          // this sweep starts L (no accumulator read)
+    int stage;          // STAGE_*
+    int seg;            // rolling segment length (y/z sweeps)
+    T inv_h;            // 1 / cell width along the sweep axis
+    T dt;               // Runge-Kutta step
+    T eps;              // WENO epsilon
+    HubbleBC hb;        // analytic boundary data (bc == HUBBLE)
+    unsigned* clamps;   // floor counter
+};
+
+// Launchers (return hipGetLastError() of the launch).
+template <class T>
+hipError_t launch_sweep(int dir, int order, const SweepArgs<T>& a, hipStream_t s);
+template <class T>
+hipError_t launch_combine(const SweepArgs<T>& a, hipStream_t s);
+template <class T>
+hipError_t launch_set_fields(T* state, const double* src, int kind, long long ncell, hipStream_t s);
+template <class T>
+hipError_t launch_get_fields(const T* state, double* dst, int kind, long long ncell,
+                             unsigned* clamps, hipStream_t s);
+template <class T>
+hipError_t launch_totals(const T* state, long long ncell, double* partials, int nblk,
+                         double* out, hipStream_t s);
+
+constexpr int kTotalsBlocks = 512;
+
+// x-sweep tile width chosen for nx (64, 32 or 16 cells; 256 threads per block).
+int choose_tile_x(int nx, int ghosts);
+// rolling segment length along y or z
+int choose_segment(int n, int ncols);
+
+}  // namespace rh

@@ -1,0 +1,496 @@
+// rh_kernels.hip -- gfx950 kernels of the WENO / SSP-RK3 hot path.
+//
+// One evaluation of L(u) (Eq. (2) of Sikorski et al., arXiv:1604.03360) is split
+// into one sweep per grid axis, in the order x, y, z; each sweep adds its flux
+// difference to an L accumulator in HBM and the last one fuses the Runge-Kutta
+// stage combine (Sec. 1).  Fields are SoA [5][nz][ny][nx], x fastest.
+//
+//  * sweep_x: x is the contiguous axis, so a 256-thread block stages a tile of
+//    TX x TY cells plus G ghost columns per side in LDS (coalesced loads, one
+//    primitive recovery and flux split per staged cell), each lane computes the
+//    numerical flux at the right face of its cell, the left faces of the tile's
+//    first column are spread over lanes as single reconstructions, and the
+//    face fluxes are exchanged through LDS for the difference.
+//  * sweep_roll<DIR>: y and z are strided axes; each lane owns one (x, w)
+//    column segment and rolls a register window of 2R cells of split fluxes
+//    along the axis, so each face flux is computed once and each cell is
+//    loaded and recovered once (plus 2R halo cells per segment).  Lanes of a
+//    wave hold 64 consecutive x, so every load and store is coalesced.
+#include "rh_internal.hpp"
+#include "../../include/rh.h"
+
+namespace rh {
+
+// ---------------------------------------------------------------------------
+// Cell loads with the boundary condition of the sweep axis
+// ---------------------------------------------------------------------------
+template <class T, int DIR>
+__device__ __forceinline__ void load_cell(const SweepArgs<T>& A, int ix, int iy, int iz, T u[5]) {
+    int c[3] = {ix, iy, iz};
+    const int nd = A.n[DIR];
+    int m = c[DIR];
+    if (m < 0 || m >= nd) {
+        if (A.bc == RH_BC_PERIODIC) {
+            m %= nd;
+            if (m < 0) m += nd;
+            c[DIR] = m;
+        } else if (A.bc == RH_BC_OUTFLOW) {
+            c[DIR] = m < 0 ? 0 : nd - 1;
+        } else {
+            double uh[5];
+            hubble_conserved(A.hb, A.hb.c0[0] + c[0] * A.hb.h[0], A.hb.c0[1] + c[1] * A.hb.h[1],
+                             A.hb.c0[2] + c[2] * A.hb.h[2], uh);
+#pragma unroll
+            for (int f = 0; f < 5; ++f) u[f] = (T)uh[f];
+            return;
+        }
+    }
+    const long long id = c[0] + (long long)A.n[0] * (c[1] + (long long)A.n[1] * c[2]);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
+}
+
+template <class T, int ORDER>
+__device__ __forceinline__ T recon_plus(const T* w, T eps) {
+    if constexpr (ORDER == 5) return weno5<T>(w[0], w[1], w[2], w[3], w[4], eps);
+    else return weno7<T>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], eps);
+}
+template <class T, int ORDER>
+__device__ __forceinline__ T recon_minus(const T* w, T eps) {
+    if constexpr (ORDER == 5) return weno5<T>(w[5], w[4], w[3], w[2], w[1], eps);
+    else return weno7<T>(w[7], w[6], w[5], w[4], w[3], w[2], w[1], eps);
+}
+
+// Accumulate L of this direction and either store L or apply the stage combine:
+// stage 1: u1 = u + dt L; stage 2: 3/4 u^n + 1/4 (u1 + dt L);
+// stage 3: 1/3 u^n + 2/3 (u2 + dt L).
+template <class T>
+__device__ __forceinline__ void epilogue(const SweepArgs<T>& A, long long id, T L[5]) {
+    if (!A.first) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) L[c] = A.lacc[c * A.fstride + id] + L[c];
+    }
+    if (A.stage == STAGE_WRITE_L) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) A.lacc[c * A.fstride + id] = L[c];
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const long long q = c * A.fstride + id;
+        T v = A.us[q] + A.dt * L[c];
+        if (A.stage == STAGE_2) v = (T)0.75 * A.u0[q] + (T)0.25 * v;
+        else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * A.u0[q] + (T)(2.0 / 3.0) * v;
+        A.uout[q] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x sweep: LDS tile
+// ---------------------------------------------------------------------------
+template <class T, int ORDER, int TX>
+__global__ void __launch_bounds__(256) sweep_x(SweepArgs<T> A) {
+    constexpr int R = (ORDER + 1) / 2, G = R, TY = 256 / TX, PW = TX + 2 * G;
+    __shared__ T sp[5 * TY * PW];
+    __shared__ T sm[5 * TY * PW];
+    const int nx = A.n[0], ny = A.n[1];
+    const int nrows = ny * A.n[2];
+    const int ntx = (nx + TX - 1) / TX;
+    const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+    const int x0 = bx * TX, r0 = by * TY;
+    const int tid = threadIdx.x;
+    unsigned clamped = 0;
+
+    for (int idx = tid; idx < TY * PW; idx += 256) {
+        const int ly = idx / PW, lx = idx - ly * PW;
+        const int row = r0 + ly, gx = x0 + lx - G;
+        if (row < nrows && gx < nx + G) {
+            T u[5], fp[5], fm[5];
+            load_cell<T, 0>(A, gx, row % ny, row / ny, u);
+            split_flux<T, 0>(u, fp, fm, clamped);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                sp[(c * TY + ly) * PW + lx] = fp[c];
+                sm[(c * TY + ly) * PW + lx] = fm[c];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, row = r0 + ly;
+    const bool active = gx < nx && row < nrows;
+    T Fr[5];
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const int o = (c * TY + ly) * PW + lx + 1;
+            Fr[c] = recon_plus<T, ORDER>(sp + o, A.eps) + recon_minus<T, ORDER>(sm + o, A.eps);
+        }
+    }
+    // left face of the tile's first column, one reconstruction per lane:
+    // job = row * 10 + component * 2 + sign
+    const bool has_ex = tid < 10 * TY;
+    T ex = (T)0;
+    if (has_ex) {
+        const int ely = tid / 10, ec = (tid % 10) >> 1, esg = tid & 1;
+        if (r0 + ely < nrows) {
+            const int o = (ec * TY + ely) * PW;   // window starts at staged column 0
+            ex = esg == 0 ? recon_plus<T, ORDER>(sp + o, A.eps) : recon_minus<T, ORDER>(sm + o, A.eps);
+        }
+    }
+    __syncthreads();
+    T* fh = sp;   // face fluxes [5][TY][TX+1]
+    T* fe = sm;   // left-face reconstructions [TY][10]
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fh[(c * TY + ly) * (TX + 1) + lx + 1] = Fr[c];
+    }
+    if (has_ex) fe[tid] = ex;
+    __syncthreads();
+    if (active) {
+        T L[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T Fl = lx == 0 ? fe[ly * 10 + c * 2] + fe[ly * 10 + c * 2 + 1]
+                                 : fh[(c * TY + ly) * (TX + 1) + lx];
+            L[c] = (Fl - Fr[c]) * A.inv_h;
+        }
+        epilogue(A, gx + (long long)nx * row, L);
+    }
+    if (clamped) atomicAdd(A.clamps, clamped);
+}
+
+// ---------------------------------------------------------------------------
+// y / z sweeps: per-lane rolling register window
+// ---------------------------------------------------------------------------
+template <class T, int ORDER, int DIR>
+__global__ void __launch_bounds__(256) sweep_roll(SweepArgs<T> A) {
+    constexpr int R = (ORDER + 1) / 2, W = 2 * R;
+    constexpr int WD = DIR == 1 ? 2 : 1;   // the other transverse axis
+    const int nx = A.n[0];
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int w = blockIdx.y * 4 + threadIdx.y;
+    if (x >= nx || w >= A.n[WD]) return;
+    const int nd = A.n[DIR];
+    const int k0 = blockIdx.z * A.seg;
+    const int kend = min(k0 + A.seg, nd);
+    const long long stride = DIR == 1 ? (long long)nx : (long long)nx * A.n[1];
+    const long long base = DIR == 1 ? x + (long long)nx * A.n[1] * w : x + (long long)nx * w;
+    unsigned clamped = 0;
+
+    auto fetch = [&](int m, T u[5]) {
+        if (m >= 0 && m < nd) {
+            const long long id = base + m * stride;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
+        } else if (DIR == 1) {
+            load_cell<T, DIR>(A, x, m, w, u);
+        } else {
+            load_cell<T, DIR>(A, x, w, m, u);
+        }
+    };
+
+    // window of interface k-1/2: cells k-R .. k+R-1
+    T wp[5][W], wm[5][W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        T u[5], fp[5], fm[5];
+        fetch(k0 - R + j, u);
+        split_flux<T, DIR>(u, fp, fm, clamped);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            wp[c][j] = fp[c];
+            wm[c][j] = fm[c];
+        }
+    }
+    T Fl[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        Fl[c] = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
+
+    for (int k = k0; k < kend; ++k) {
+        T u[5], fp[5], fm[5];
+        fetch(k + R, u);
+        split_flux<T, DIR>(u, fp, fm, clamped);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+#pragma unroll
+            for (int j = 0; j < W - 1; ++j) {
+                wp[c][j] = wp[c][j + 1];
+                wm[c][j] = wm[c][j + 1];
+            }
+            wp[c][W - 1] = fp[c];
+            wm[c][W - 1] = fm[c];
+        }
+        T L[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T Fr = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
+            L[c] = (Fl[c] - Fr) * A.inv_h;
+            Fl[c] = Fr;
+        }
+        epilogue(A, base + k * stride, L);
+    }
+    if (clamped) atomicAdd(A.clamps, clamped);
+}
+
+// Stage combine with L = 0 (grids with no axis longer than one cell).
+template <class T>
+__global__ void combine_zero_L(SweepArgs<T> A) {
+    const long long n = A.fstride;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        T L[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+        SweepArgs<T> B = A;
+        B.first = 1;
+        epilogue(B, i, L);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Field conversion
+// ---------------------------------------------------------------------------
+__device__ inline void prim_to_cons(const double pr[5], double u[5]) {
+    const double e = pr[0], vx = pr[1], vy = pr[2], vz = pr[3], n = pr[4];
+    const double p = e / 3.0;
+    const double g2 = 1.0 / (1.0 - (vx * vx + vy * vy + vz * vz));
+    const double w = e + p;
+    u[0] = w * g2 - p;
+    u[1] = w * g2 * vx;
+    u[2] = w * g2 * vy;
+    u[3] = w * g2 * vz;
+    u[4] = n * sqrt(g2);
+}
+
+// Full FP64 primitive recovery (e, v, n) with the same floors as the sweeps.
+__device__ inline void cons_to_prim(const double u[5], double pr[5], unsigned& clamped) {
+    const double E = u[0], N = u[4];
+    double Mx = u[1], My = u[2], Mz = u[3];
+    if (E < kEFloor) {
+        pr[0] = (E > 0.0 ? E : 0.0);
+        pr[1] = pr[2] = pr[3] = 0.0;
+        pr[4] = N;
+        ++clamped;
+        return;
+    }
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    const double cap = (1.0 - kVDelta) * E * E;
+    if (M2 > cap) {
+        const double s = sqrt(cap / M2);
+        Mx *= s; My *= s; Mz *= s;
+        M2 = cap;
+        ++clamped;
+    }
+    const double D = sqrt(4.0 * E * E - 3.0 * M2);
+    const double k = 3.0 / (2.0 * E + D);
+    pr[0] = 3.0 * ((E * E - M2) / (E + D));
+    pr[1] = k * Mx;
+    pr[2] = k * My;
+    pr[3] = k * Mz;
+    pr[4] = N * sqrt(1.0 - k * k * M2);
+}
+
+template <class T>
+__global__ void set_fields_kernel(T* state, const double* src, int kind, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double a[5], u[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) a[f] = src[f * n + i];
+        if (kind == RH_FIELDS_PRIMITIVE) prim_to_cons(a, u);
+        else {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) u[f] = a[f];
+        }
+#pragma unroll
+        for (int f = 0; f < 5; ++f) state[f * n + i] = (T)u[f];
+    }
+}
+
+template <class T>
+__global__ void get_fields_kernel(const T* state, double* dst, int kind, long long n,
+                                  unsigned* clamps) {
+    unsigned clamped = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double u[5], o[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f] = (double)state[f * n + i];
+        if (kind == RH_FIELDS_PRIMITIVE) cons_to_prim(u, o, clamped);
+        else {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) o[f] = u[f];
+        }
+#pragma unroll
+        for (int f = 0; f < 5; ++f) dst[f * n + i] = o[f];
+    }
+    if (clamped) atomicAdd(clamps, clamped);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 totals: fixed partition of cells over blocks, fixed-order tree in LDS,
+// then one block sums the partials in a fixed order -- deterministic.
+// partials: [6][nblk] (5 sums and the count of cells with a non-finite value).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) totals_pass1(const T* u, long long n, double* partials,
+                                                    int nblk) {
+    __shared__ double red[6][256];
+    const long long chunk = (n + nblk - 1) / nblk;
+    const long long beg = blockIdx.x * chunk;
+    const long long end = min(n, beg + chunk);
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (long long i = beg + threadIdx.x; i < end; i += 256) {
+        bool bad = false;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            const double v = (double)u[f * n + i];
+            s[f] += v;
+            bad |= !isfinite(v);
+        }
+        s[5] += bad ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) red[f][threadIdx.x] = s[f];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partials[threadIdx.x * nblk + blockIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) totals_pass2(const double* partials, int nblk, double* out) {
+    __shared__ double red[6][256];
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s[f] += partials[f * nblk + b];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) red[f][threadIdx.x] = s[f];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch configuration
+// ---------------------------------------------------------------------------
+int choose_tile_x(int nx, int ghosts) {
+    // fewest staged cells per useful cell: padded tiles plus their ghost columns
+    int best = 64;
+    double best_cost = 1e300;
+    for (int tx : {64, 32, 16}) {
+        const int ntx = (nx + tx - 1) / tx;
+        const double cost = ntx * (tx + 2.0 * ghosts * 0.25) / nx;
+        if (cost < best_cost - 1e-12) {
+            best_cost = cost;
+            best = tx;
+        }
+    }
+    return best;
+}
+
+int choose_segment(int n, int ncol_lanes) {
+    // enough lanes to fill the chip (about 2^19), segments no shorter than 32 cells
+    const long long target = 1LL << 19;
+    long long nseg = (target + ncol_lanes - 1) / ncol_lanes;
+    const long long max_seg = (n + 31) / 32;
+    if (nseg > max_seg) nseg = max_seg;
+    if (nseg < 1) nseg = 1;
+    return (int)((n + nseg - 1) / nseg);
+}
+
+template <class T, int ORDER>
+static hipError_t launch_x(const SweepArgs<T>& a, hipStream_t s) {
+    const int tx = choose_tile_x(a.n[0], (ORDER + 1) / 2);
+    const int ty = 256 / tx;
+    const long long ntx = (a.n[0] + tx - 1) / tx;
+    const long long nrt = ((long long)a.n[1] * a.n[2] + ty - 1) / ty;
+    const dim3 grid((unsigned)(ntx * nrt));
+    if (tx == 64) sweep_x<T, ORDER, 64><<<grid, 256, 0, s>>>(a);
+    else if (tx == 32) sweep_x<T, ORDER, 32><<<grid, 256, 0, s>>>(a);
+    else sweep_x<T, ORDER, 16><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <class T, int ORDER, int DIR>
+static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
+    const int wd = DIR == 1 ? 2 : 1;
+    const unsigned gx = (a.n[0] + 63) / 64, gy = (a.n[wd] + 3) / 4;
+    const int seg = choose_segment(a.n[DIR], (int)(gx * 64 * gy * 4));
+    a.seg = seg;
+    const unsigned gz = (a.n[DIR] + seg - 1) / seg;
+    sweep_roll<T, ORDER, DIR><<<dim3(gx, gy, gz), dim3(64, 4), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_sweep(int dir, int order, const SweepArgs<T>& a, hipStream_t s) {
+    if (order == 5) {
+        if (dir == 0) return launch_x<T, 5>(a, s);
+        if (dir == 1) return launch_roll<T, 5, 1>(a, s);
+        return launch_roll<T, 5, 2>(a, s);
+    }
+    if (dir == 0) return launch_x<T, 7>(a, s);
+    if (dir == 1) return launch_roll<T, 7, 1>(a, s);
+    return launch_roll<T, 7, 2>(a, s);
+}
+
+static unsigned elementwise_blocks(long long n) {
+    long long b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <class T>
+hipError_t launch_combine(const SweepArgs<T>& a, hipStream_t s) {
+    combine_zero_L<T><<<elementwise_blocks(a.fstride), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_set_fields(T* state, const double* src, int kind, long long n, hipStream_t s) {
+    set_fields_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(state, src, kind, n);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_get_fields(const T* state, double* dst, int kind, long long n, unsigned* clamps,
+                             hipStream_t s) {
+    get_fields_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(state, dst, kind, n, clamps);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_totals(const T* state, long long n, double* partials, int nblk, double* out,
+                         hipStream_t s) {
+    totals_pass1<T><<<nblk, 256, 0, s>>>(state, n, partials, nblk);
+    totals_pass2<<<1, 256, 0, s>>>(partials, nblk, out);
+    return hipGetLastError();
+}
+
+#define RH_INSTANTIATE(T)                                                                         \
+    template hipError_t launch_sweep<T>(int, int, const SweepArgs<T>&, hipStream_t);               \
+    template hipError_t launch_combine<T>(const SweepArgs<T>&, hipStream_t);                       \
+    template hipError_t launch_set_fields<T>(T*, const double*, int, long long, hipStream_t);      \
+    template hipError_t launch_get_fields<T>(const T*, double*, int, long long, unsigned*,         \
+                                             hipStream_t);                                         \
+    template hipError_t launch_totals<T>(const T*, long long, double*, int, double*, hipStream_t);
+
+RH_INSTANTIATE(float)
+RH_INSTANTIATE(double)
+
+}  // namespace rh

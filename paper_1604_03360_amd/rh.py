@@ -1,0 +1,240 @@
+"""Python binding of the C ABI in include/rh.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: all work runs in the gfx950 kernels of librh.so.
+PyTorch is used only to own device memory and to supply the HIP stream.
+
+The binding fails loudly (ImportError) when librh.so has not been built; there
+is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librh.so")
+
+RH_OK, RH_E_INVAL, RH_E_NOMEM, RH_E_HIP, RH_E_STATE, RH_E_NOTSUP, RH_E_PHYS = 0, -1, -2, -3, -4, -5, -6
+RH_PREC_FP64, RH_PREC_FP32 = 0, 1
+RH_BC_PERIODIC, RH_BC_OUTFLOW, RH_BC_HUBBLE = 0, 1, 2
+RH_FIELDS_CONSERVED, RH_FIELDS_PRIMITIVE = 0, 1
+RH_KERNEL_SWEEP_X, RH_KERNEL_SWEEP_Y, RH_KERNEL_SWEEP_Z, RH_KERNEL_OTHER = 0, 1, 2, 3
+RH_KERNEL_CLASSES = 4
+KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other")
+
+
+class rh_grid_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("scheme", ctypes.c_int), ("precision", ctypes.c_int), ("bc", ctypes.c_int * 3),
+                ("weno_eps", ctypes.c_double), ("hubble_t0", ctypes.c_double),
+                ("hubble_e0", ctypes.c_double), ("hubble_n0", ctypes.c_double),
+                ("strict", ctypes.c_int)]
+
+
+class RHError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("rh status %d: %s" % (status, message))
+        self.status = status
+
+
+_lib = None
+
+
+def library():
+    """Load librh.so (built by paper_1604_03360_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librh.so is not built (run python -m paper_1604_03360_amd.build); "
+                              "there is no fallback implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i, d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.rh_last_error.restype = ctypes.c_char_p
+        L.rh_version.restype = ctypes.c_char_p
+        L.rh_plan_create.argtypes = [pp, ctypes.POINTER(rh_grid_desc)]
+        L.rh_plan_destroy.argtypes = [vp]
+        L.rh_plan_destroy.restype = None
+        L.rh_state_bytes.argtypes = [vp]
+        L.rh_state_bytes.restype = ctypes.c_size_t
+        L.rh_workspace_bytes.argtypes = [vp]
+        L.rh_workspace_bytes.restype = ctypes.c_size_t
+        L.rh_bind.argtypes = [vp, vp, vp, vp]
+        L.rh_set_fields.argtypes = [vp, vp, i]
+        L.rh_get_fields.argtypes = [vp, vp, i]
+        L.rh_apply_L.argtypes = [vp, d, vp]
+        L.rh_step.argtypes = [vp, d, i, dp]
+        L.rh_totals.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.rh_reset_counters.argtypes = [vp]
+        L.rh_set_timing.argtypes = [vp, i]
+        L.rh_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), i]
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != RH_OK:
+        raise RHError(status, library().rh_last_error().decode())
+    return status
+
+
+def rh_version():
+    return library().rh_version().decode()
+
+
+def rh_last_error():
+    return library().rh_last_error().decode()
+
+
+def rh_plan_create(desc):
+    plan = ctypes.c_void_p()
+    _check(library().rh_plan_create(ctypes.byref(plan), ctypes.byref(desc)))
+    return plan
+
+
+def rh_plan_destroy(plan):
+    library().rh_plan_destroy(plan)
+
+
+def rh_state_bytes(plan):
+    return library().rh_state_bytes(plan)
+
+
+def rh_workspace_bytes(plan):
+    return library().rh_workspace_bytes(plan)
+
+
+def rh_bind(plan, state_ptr, workspace_ptr, stream_ptr):
+    _check(library().rh_bind(plan, ctypes.c_void_p(state_ptr), ctypes.c_void_p(workspace_ptr),
+                             ctypes.c_void_p(stream_ptr)))
+
+
+def rh_set_fields(plan, src_ptr, kind):
+    _check(library().rh_set_fields(plan, ctypes.c_void_p(src_ptr), kind))
+
+
+def rh_get_fields(plan, dst_ptr, kind):
+    _check(library().rh_get_fields(plan, ctypes.c_void_p(dst_ptr), kind))
+
+
+def rh_apply_L(plan, t, L_ptr):
+    _check(library().rh_apply_L(plan, float(t), ctypes.c_void_p(L_ptr)))
+
+
+def rh_step(plan, dt, n_steps, t):
+    tt = ctypes.c_double(t)
+    _check(library().rh_step(plan, float(dt), int(n_steps), ctypes.byref(tt)))
+    return tt.value
+
+
+def rh_totals(plan):
+    out = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_longlong * 2)()
+    _check(library().rh_totals(plan, out, cnt))
+    return list(out), list(cnt)
+
+
+def rh_reset_counters(plan):
+    _check(library().rh_reset_counters(plan))
+
+
+def rh_set_timing(plan, enable):
+    _check(library().rh_set_timing(plan, int(bool(enable))))
+
+
+def rh_kernel_times(plan):
+    ms = (ctypes.c_double * RH_KERNEL_CLASSES)()
+    cnt = (ctypes.c_longlong * RH_KERNEL_CLASSES)()
+    _check(library().rh_kernel_times(plan, ms, cnt, RH_KERNEL_CLASSES))
+    return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(RH_KERNEL_CLASSES)}
+
+
+def make_desc(shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC,) * 3,
+              eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False):
+    d = rh_grid_desc()
+    d.nx, d.ny, d.nz = (int(s) for s in shape)
+    d.dx, d.dy, d.dz = (float(v) for v in h)
+    d.x0, d.y0, d.z0 = (float(v) for v in c0)
+    d.scheme = int(scheme)
+    d.precision = int(precision)
+    for a in range(3):
+        d.bc[a] = int(bc[a])
+    d.weno_eps = float(eps)
+    d.hubble_t0, d.hubble_e0, d.hubble_n0 = (float(v) for v in hub)
+    d.strict = int(bool(strict))
+    return d
+
+
+class Hydro:
+    """One grid on the GPU: torch owns the state and workspace tensors, the
+    library does all the work on torch's current stream."""
+
+    def __init__(self, shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC,) * 3,
+                 eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False, device="cuda", t=0.0):
+        import torch
+        self.torch = torch
+        self.shape = tuple(int(s) for s in shape)
+        self.desc = make_desc(shape, h, c0, scheme, precision, bc, eps, hub, strict)
+        self.plan = rh_plan_create(self.desc)
+        self.dtype = torch.float32 if precision == RH_PREC_FP32 else torch.float64
+        nx, ny, nz = self.shape
+        self.device = torch.device(device)
+        self.state = torch.zeros((5, nz, ny, nx), dtype=self.dtype, device=self.device)
+        self.workspace = torch.zeros((3, 5, nz, ny, nx), dtype=self.dtype, device=self.device)
+        assert self.state.numel() * self.state.element_size() == rh_state_bytes(self.plan)
+        assert self.workspace.numel() * self.workspace.element_size() == rh_workspace_bytes(self.plan)
+        self.t = float(t)
+        self.bind()
+
+    @classmethod
+    def from_spec(cls, spec, precision=RH_PREC_FP64, scheme=None, **kw):
+        return cls(spec["shape"], spec["h"], spec["c0"], scheme=scheme or spec["order"],
+                   precision=precision, bc=spec["bc"], eps=spec.get("eps", 1e-6),
+                   hub=spec.get("hub", (10.0, 1.0, 0.5)), t=spec.get("t0", 0.0), **kw)
+
+    def stream_ptr(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def bind(self):
+        rh_bind(self.plan, self.state.data_ptr(), self.workspace.data_ptr(), self.stream_ptr())
+
+    def set_primitive(self, prim):
+        src = self.torch.as_tensor(prim, dtype=self.torch.float64).to(self.device).contiguous()
+        rh_set_fields(self.plan, src.data_ptr(), RH_FIELDS_PRIMITIVE)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def set_conserved(self, con):
+        src = self.torch.as_tensor(con, dtype=self.torch.float64).to(self.device).contiguous()
+        rh_set_fields(self.plan, src.data_ptr(), RH_FIELDS_CONSERVED)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def get(self, kind=RH_FIELDS_CONSERVED):
+        nx, ny, nz = self.shape
+        dst = self.torch.empty((5, nz, ny, nx), dtype=self.torch.float64, device=self.device)
+        rh_get_fields(self.plan, dst.data_ptr(), kind)
+        return dst.cpu().numpy()
+
+    def apply_L(self, t=None):
+        out = self.torch.empty_like(self.state)
+        rh_apply_L(self.plan, self.t if t is None else t, out.data_ptr())
+        return out
+
+    def step(self, dt, n_steps=1):
+        self.t = rh_step(self.plan, dt, n_steps, self.t)
+        return self.t
+
+    def totals(self):
+        return rh_totals(self.plan)
+
+    def close(self):
+        if self.plan is not None:
+            self.torch.cuda.current_stream(self.device).synchronize()
+            rh_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,69 @@
+"""The C-ABI library loads on any host and exports every entry point that
+include/rh.h declares (no compute calls: those need the GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rh.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(rh_[A-Za-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1604_03360_amd import rh
+    if not os.path.exists(rh.LIB_PATH):
+        from paper_1604_03360_amd import build
+        build.build()
+    return rh.library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rh_plan_create", "rh_bind", "rh_step", "rh_get_fields", "rh_set_fields",
+                     "rh_apply_L", "rh_totals", "rh_plan_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_header():
+    from paper_1604_03360_amd import rh
+    # ints: nx ny nz | pad | 6 doubles | scheme precision bc[3] | pad | 4 doubles | strict | pad
+    assert ctypes.sizeof(rh.rh_grid_desc) == 4 * 3 + 4 + 8 * 6 + 4 * 5 + 4 + 8 * 4 + 8
+    assert rh.rh_grid_desc.dx.offset == 16
+    assert rh.rh_grid_desc.scheme.offset == 64
+    assert rh.rh_grid_desc.weno_eps.offset == 88
+
+
+def test_invalid_descriptions_are_rejected_without_a_gpu(lib):
+    from paper_1604_03360_amd import rh
+    bad = [dict(scheme=6), dict(precision=3), dict(bc=(0, 0, 9)), dict(h=(0.1, -1.0, 0.1)),
+           dict(shape=(0, 4, 4))]
+    for kw in bad:
+        args = dict(shape=(8, 8, 8), h=(0.1,) * 3, c0=(0, 0, 0))
+        args.update(kw)
+        d = rh.make_desc(**args)
+        with pytest.raises(rh.RHError) as ei:
+            rh.rh_plan_create(d)
+        assert ei.value.status == rh.RH_E_INVAL
+        assert rh.rh_last_error()
+
+
+def test_null_plan_calls_fail_cleanly(lib):
+    from paper_1604_03360_amd import rh
+    assert lib.rh_step(None, 0.1, 1, None) == rh.RH_E_INVAL
+    assert lib.rh_apply_L(None, 0.0, None) == rh.RH_E_INVAL
+    assert lib.rh_state_bytes(None) == 0
+    lib.rh_plan_destroy(None)

@@ -35,7 +35,9 @@ MUTATIONS = [
     ("outflow map", "c[d] = m < 0 ? 0 : nd - 1;", "c[d] = m < 0 ? 1 : nd - 1;"),
     ("weight exponent", "alpha[k] = d[k] / (g * g);", "alpha[k] = d[k] / g;"),
     ("primitive pressure", "p = (E * E - M2) / (E + D);", "p = (E * E - M2) / (E + 1.01 * D);"),
-    ("weno7 beta", "+ 547.0 * p3 * p3) / 240.0;", "+ 547.0 * p3 * p3) / 241.0;"),
+    ("weno7 beta", "+ 3129.0 / 80.0 * a3[k] * a3[k];", "+ 3129.0 / 81.0 * a3[k] * a3[k];"),
+    ("weno7 beta stencil", "a1[1] = (5.0 * m2 - 27.0 * m1 + 15.0 * z0 + 7.0 * p1) / 24.0;",
+     "a1[1] = (5.0 * m2 - 27.0 * m1 + 15.0 * z0 + 7.0 * p2) / 24.0;"),
     ("weno7 candidate", "q[2] = (-m1 + 7.0 * z0 + 7.0 * p1 - p2) / 12.0;",
      "q[2] = (-m1 + 7.0 * z0 + 7.0 * p1 - p2) / 12.1;"),
     ("weno7 linear weights",
