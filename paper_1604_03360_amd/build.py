@@ -20,13 +20,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose=False):
-    objdir = os.path.join(HERE, "_build")
+def build(verbose=False, out=None, defines=(), objdir=None):
+    """Compile and link librh.so (or `out`), optionally with extra -D defines."""
+    objdir = objdir or os.path.join(HERE, "_build")
+    lib = out or LIB
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(HERE, "csrc", src),
+                                                                "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
@@ -34,13 +37,13 @@ def build(verbose=False):
 
     with concurrent.futures.ThreadPoolExecutor(len(SOURCES)) as pool:
         objs = list(pool.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -42,10 +42,23 @@ __device__ inline void hubble_conserved(const HubbleBC& hb, double x, double y, 
     u[4] = n * sqrt(g2);
 }
 
+// Reciprocals.  FP32: the hardware reciprocal (about 1 ulp).  FP64: the
+// hardware estimate refined by two Newton-Raphson steps r <- r + r (1 - x r),
+// which carries the estimate to full double precision for the normal-range
+// arguments used here (weight sums, (2E + D)(E + D)).
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Closed-form primitive recovery for p = e/3 (FP64):
 //   M^2 = |M|^2, D = sqrt(4E^2 - 3M^2), v = 3M/(2E + D), p = (E^2 - M^2)/(E + D).
 // Only the velocity along the sweep axis and p are needed for the flux.  Both
-// divisions share one reciprocal of (2E + D)(E + D).
+// divisions share one (Newton-refined) reciprocal of (2E + D)(E + D).
 template <int DIR>
 __device__ __forceinline__ void recover_vp(double E, double Mx, double My, double Mz,
                                            double& vd, double& p, unsigned& clamped) {
@@ -67,7 +80,7 @@ __device__ __forceinline__ void recover_vp(double E, double Mx, double My, doubl
     const double D = sqrt(4.0 * E2 - 3.0 * M2);
     const double a = 2.0 * E + D;
     const double b = E + D;
-    const double r = 1.0 / (a * b);
+    const double r = fast_rcp(a * b);
     vd = 3.0 * b * r * Md;
     p = (E2 - M2) * a * r;
 }
@@ -91,107 +104,90 @@ __device__ __forceinline__ void split_flux(const T u[5], T fp[5], T fm[5], unsig
     }
 }
 
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
-
-// WENO5: s0..s4 = f_{i-2..i+2}; left-biased value at i+1/2.
-// Candidates q_k, indicators beta_k (Jiang-Shu), linear weights (1, 6, 3)/10.
-// omega_k = alpha_k / sum(alpha), alpha_k = d_k / (eps + beta_k)^2, evaluated with
-// one reciprocal as d_k prod_{j != k} g_j / sum_k(...), g_j = (eps + beta_j)^2.
+// WENO5: s0..s4 = f_{i-2..i+2}; left-biased value at i+1/2 (Jiang-Shu).
+// Written in the differences E_j = s_j - s_{j-1} about the centre c = s2:
+//   q_k - c:  (-E1/3 + 5 E2/6), (E2/6 + E3/3), (2 E3/3 - E4/6)
+//   beta_k = 13/12 A_k^2 + 1/4 B_k^2 with A = (E2-E1, E3-E2, E4-E3),
+//            B = (3E2-E1, E2+E3, E4-3E3);
+// 4 beta_k = 13/3 A^2 + B^2 is used with 4 eps (the common factor cancels), and
+// alpha_k = d_k / (eps + beta_k)^2 is evaluated with one reciprocal as
+// d_k prod_{j != k} g_j / sum(...), g_j = (4 eps + 4 beta_j)^2, d = (1, 6, 3)/10.
 template <class T>
-__device__ __forceinline__ T weno5(T s0, T s1, T s2, T s3, T s4, T eps) {
-    const T c13 = (T)(1.0 / 3.0), c16 = (T)(1.0 / 6.0), c56 = (T)(5.0 / 6.0);
-    const T c76 = (T)(7.0 / 6.0), c116 = (T)(11.0 / 6.0), c1312 = (T)(13.0 / 12.0), q4 = (T)0.25;
-    const T q0 = c13 * s0 - c76 * s1 + c116 * s2;
-    const T q1 = -c16 * s1 + c56 * s2 + c13 * s3;
-    const T q2 = c13 * s2 + c56 * s3 - c16 * s4;
-    const T a0 = s0 - (T)2 * s1 + s2, b0 = s0 - (T)4 * s1 + (T)3 * s2;
-    const T a1 = s1 - (T)2 * s2 + s3, b1 = s1 - s3;
-    const T a2 = s2 - (T)2 * s3 + s4, b2 = (T)3 * s2 - (T)4 * s3 + s4;
-    T g0 = eps + (c1312 * a0 * a0 + q4 * b0 * b0);
-    T g1 = eps + (c1312 * a1 * a1 + q4 * b1 * b1);
-    T g2 = eps + (c1312 * a2 * a2 + q4 * b2 * b2);
+__device__ __forceinline__ T weno5(T s0, T s1, T s2, T s3, T s4, T eps4) {
+    const T E1 = s1 - s0, E2 = s2 - s1, E3 = s3 - s2, E4 = s4 - s3;
+    const T dq0 = (T)(5.0 / 6.0) * E2 - (T)(1.0 / 3.0) * E1;
+    const T dq1 = (T)(1.0 / 6.0) * E2 + (T)(1.0 / 3.0) * E3;
+    const T dq2 = (T)(2.0 / 3.0) * E3 - (T)(1.0 / 6.0) * E4;
+    const T A0 = E2 - E1, A1 = E3 - E2, A2 = E4 - E3;
+    const T B0 = (T)3 * E2 - E1, B1 = E2 + E3, B2 = E4 - (T)3 * E3;
+    const T c133 = (T)(13.0 / 3.0);
+    T g0 = (c133 * A0) * A0 + (B0 * B0 + eps4);
+    T g1 = (c133 * A1) * A1 + (B1 * B1 + eps4);
+    T g2 = (c133 * A2) * A2 + (B2 * B2 + eps4);
     g0 *= g0;
     g1 *= g1;
     g2 *= g2;
-    const T w0 = (T)0.1 * (g1 * g2);
-    const T w1 = (T)0.6 * (g0 * g2);
-    const T w2 = (T)0.3 * (g0 * g1);
-    return (w0 * q0 + w1 * q1 + w2 * q2) * fast_rcp(w0 + w1 + w2);
+    // w0 = 0.1 g1 g2, w1 = 0.6 g0 g2, w2 = 0.3 g0 g1, factored through g2
+    const T e0 = (T)0.1 * g1, e1 = (T)0.6 * g0;
+    const T P = (T)0.5 * (e1 * g1);
+    const T num = g2 * (e0 * dq0 + e1 * dq1) + P * dq2;
+    const T den = g2 * (e0 + e1) + P;
+    return s2 + num * fast_rcp(den);
 }
 
-// WENO7 smoothness indicators beta_k = sum_{l=1..3} int_cell (d^l p_k/dx^l)^2 of
-// the cubic candidate p_k = a0 + a1 x + a2 x^2 + a3 x^3 (x in cells):
-// beta_k = a1^2 + a1 a3 / 2 + 13/3 a2^2 + 3129/80 a3^2, with a1..a3 difference
-// combinations of the stencil (well conditioned in FP32 as well as FP64).
-template <class T>
-__device__ __forceinline__ void weno7_beta(T m3, T m2, T m1, T z0, T p1, T p2, T p3, T b[4]) {
-    const T c24 = (T)(1.0 / 24.0), c6 = (T)(1.0 / 6.0), h = (T)0.5;
-    const T k2 = (T)(13.0 / 3.0), k3 = (T)(3129.0 / 80.0);
-    T a1[4], a2[4], a3[4];
-    a1[0] = c24 * (-(T)7 * m3 + (T)33 * m2 - (T)69 * m1 + (T)43 * z0);
-    a2[0] = h * (-m3 + (T)4 * m2 - (T)5 * m1 + (T)2 * z0);
-    a3[0] = c6 * (-m3 + (T)3 * (m2 - m1) + z0);
-    a1[1] = c24 * ((T)5 * m2 - (T)27 * m1 + (T)15 * z0 + (T)7 * p1);
-    a2[1] = h * (m1 - (T)2 * z0 + p1);
-    a3[1] = c6 * (-m2 + (T)3 * (m1 - z0) + p1);
-    a1[2] = c24 * (-(T)7 * m1 - (T)15 * z0 + (T)27 * p1 - (T)5 * p2);
-    a2[2] = a2[1];
-    a3[2] = c6 * (-m1 + (T)3 * (z0 - p1) + p2);
-    a1[3] = c24 * (-(T)43 * z0 + (T)69 * p1 - (T)33 * p2 + (T)7 * p3);
-    a2[3] = h * ((T)2 * z0 - (T)5 * p1 + (T)4 * p2 - p3);
-    a3[3] = c6 * (-z0 + (T)3 * (p1 - p2) + p3);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        b[k] = a1[k] * (a1[k] + h * a3[k]) + k2 * a2[k] * a2[k] + k3 * a3[k] * a3[k];
-}
-
-// WENO7: s0..s6 = f_{i-3..i+3}; linear weights (1, 12, 18, 4)/35.
+// WENO7: s0..s6 = f_{i-3..i+3}; linear weights (1, 12, 18, 4)/35.  With
+// D_j = s_j - s_{j-1} and c = s3, the candidates are c + dq_k and the cubic
+// candidate p_k = a0 + a1 x + a2 x^2 + a3 x^3 gives
+// beta_k = a1^2 + a1 a3 / 2 + 13/3 a2^2 + 3129/80 a3^2 (the sum of the cell
+// integrals of its squared first three derivatives).  a2 and a3 are carried
+// pre-scaled by sqrt(13/3) and sqrt(3129/80).
 template <class T>
 __device__ __forceinline__ T weno7(T s0, T s1, T s2, T s3, T s4, T s5, T s6, T eps) {
-    const T c12 = (T)(1.0 / 12.0);
-    const T q0 = c12 * (-(T)3 * s0 + (T)13 * s1 - (T)23 * s2 + (T)25 * s3);
-    const T q1 = c12 * (s1 - (T)5 * s2 + (T)13 * s3 + (T)3 * s4);
-    const T q2 = c12 * (-s2 + (T)7 * s3 + (T)7 * s4 - s5);
-    const T q3 = c12 * ((T)3 * s3 + (T)13 * s4 - (T)5 * s5 + s6);
-    T b[4];
-    weno7_beta(s0, s1, s2, s3, s4, s5, s6, b);
-    T g[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        g[k] = eps + b[k];
-        g[k] *= g[k];
-    }
+    const T D1 = s1 - s0, D2 = s2 - s1, D3 = s3 - s2, D4 = s4 - s3, D5 = s5 - s4, D6 = s6 - s5;
+    const T dq0 = (T)0.25 * D1 - (T)(5.0 / 6.0) * D2 + (T)(13.0 / 12.0) * D3;
+    const T dq1 = (T)(1.0 / 3.0) * D3 - (T)(1.0 / 12.0) * D2 + (T)0.25 * D4;
+    const T dq2 = (T)(1.0 / 12.0) * (D3 - D5) + (T)0.5 * D4;
+    const T dq3 = (T)0.75 * D4 - (T)(1.0 / 3.0) * D5 + (T)(1.0 / 12.0) * D6;
+    const T r2 = (T)2.0816659994661326;    // sqrt(13/3)
+    const T kk = (T)(0.5 / 6.253998720818545);   // 1 / (2 sqrt(3129/80))
+    const T a1_0 = (T)(7.0 / 24.0) * D1 - (T)(13.0 / 12.0) * D2 + (T)(43.0 / 24.0) * D3;
+    const T a1_1 = (T)(11.0 / 12.0) * D3 - (T)(5.0 / 24.0) * D2 + (T)(7.0 / 24.0) * D4;
+    const T a1_2 = (T)(7.0 / 24.0) * D3 + (T)(11.0 / 12.0) * D4 - (T)(5.0 / 24.0) * D5;
+    const T a1_3 = (T)(43.0 / 24.0) * D4 - (T)(13.0 / 12.0) * D5 + (T)(7.0 / 24.0) * D6;
+    const T a2_0 = (T)(0.5 * 2.0816659994661326) * D1 - (T)(1.5 * 2.0816659994661326) * D2 + r2 * D3;
+    const T a2_1 = (T)(0.5 * 2.0816659994661326) * (D4 - D3);
+    const T a2_3 = (T)(1.5 * 2.0816659994661326) * D5 - r2 * D4 - (T)(0.5 * 2.0816659994661326) * D6;
+    const T c6 = (T)(6.253998720818545 / 6.0);
+    const T a3_0 = c6 * ((D1 + D3) - (T)2 * D2);
+    const T a3_1 = c6 * ((D2 + D4) - (T)2 * D3);
+    const T a3_2 = c6 * ((D3 + D5) - (T)2 * D4);
+    const T a3_3 = c6 * ((D4 + D6) - (T)2 * D5);
+    T g0 = a1_0 * (a1_0 + kk * a3_0) + (a2_0 * a2_0 + (a3_0 * a3_0 + eps));
+    T g1 = a1_1 * (a1_1 + kk * a3_1) + (a2_1 * a2_1 + (a3_1 * a3_1 + eps));
+    T g2 = a1_2 * (a1_2 + kk * a3_2) + (a2_1 * a2_1 + (a3_2 * a3_2 + eps));
+    T g3 = a1_3 * (a1_3 + kk * a3_3) + (a2_3 * a2_3 + (a3_3 * a3_3 + eps));
+    g0 *= g0;
+    g1 *= g1;
+    g2 *= g2;
+    g3 *= g3;
     T w0, w1, w2, w3;
     if constexpr (sizeof(T) == 8) {
-        // FP64: one division via products of the other three squared terms
-        const T g01 = g[0] * g[1], g23 = g[2] * g[3];
-        w0 = (T)(1.0 / 35.0) * (g[1] * g23);
-        w1 = (T)(12.0 / 35.0) * (g[0] * g23);
-        w2 = (T)(18.0 / 35.0) * (g01 * g[3]);
-        w3 = (T)(4.0 / 35.0) * (g01 * g[2]);
+        // FP64: one reciprocal via products of the other three squared terms
+        const T g01 = g0 * g1, g23 = g2 * g3;
+        w0 = (T)(1.0 / 35.0) * (g1 * g23);
+        w1 = (T)(12.0 / 35.0) * (g0 * g23);
+        w2 = (T)(18.0 / 35.0) * (g01 * g3);
+        w3 = (T)(4.0 / 35.0) * (g01 * g2);
     } else {
         // FP32: products of three squared terms can overflow; use reciprocals
-        w0 = (T)(1.0 / 35.0) * fast_rcp(g[0]);
-        w1 = (T)(12.0 / 35.0) * fast_rcp(g[1]);
-        w2 = (T)(18.0 / 35.0) * fast_rcp(g[2]);
-        w3 = (T)(4.0 / 35.0) * fast_rcp(g[3]);
+        w0 = (T)(1.0 / 35.0) * fast_rcp(g0);
+        w1 = (T)(12.0 / 35.0) * fast_rcp(g1);
+        w2 = (T)(18.0 / 35.0) * fast_rcp(g2);
+        w3 = (T)(4.0 / 35.0) * fast_rcp(g3);
     }
-    return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) * fast_rcp(w0 + w1 + w2 + w3);
-}
-
-// Numerical flux at an interface from a window of 2R cells: w[j] holds the
-// split fluxes of cell (i - R + 1 + j), j = 0 .. 2R-1, for the interface i+1/2.
-// F = fhat+ (left-biased on f+) + fhat- (mirrored, right-biased on f-).
-template <class T, int ORDER>
-__device__ __forceinline__ T interface_flux(const T* wp, const T* wm, T eps) {
-    if constexpr (ORDER == 5) {
-        return weno5<T>(wp[0], wp[1], wp[2], wp[3], wp[4], eps)
-             + weno5<T>(wm[5], wm[4], wm[3], wm[2], wm[1], eps);
-    } else {
-        return weno7<T>(wp[0], wp[1], wp[2], wp[3], wp[4], wp[5], wp[6], eps)
-             + weno7<T>(wm[7], wm[6], wm[5], wm[4], wm[3], wm[2], wm[1], eps);
-    }
+    const T num = (w0 * dq0 + w1 * dq1) + (w2 * dq2 + w3 * dq3);
+    const T den = (w0 + w1) + (w2 + w3);
+    return s3 + num * fast_rcp(den);
 }
 
 }  // namespace rh

@@ -16,6 +16,8 @@
 //    along the axis, so each face flux is computed once and each cell is
 //    loaded and recovered once (plus 2R halo cells per segment).  Lanes of a
 //    wave hold 64 consecutive x, so every load and store is coalesced.
+#include <stdlib.h>
+
 #include "rh_internal.hpp"
 #include "../../include/rh.h"
 
@@ -50,14 +52,17 @@ __device__ __forceinline__ void load_cell(const SweepArgs<T>& A, int ix, int iy,
     for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
 }
 
+// One reconstruction from a window of 2R split fluxes of cells i-R+1 .. i+R
+// (interface i+1/2): plus = left-biased on f+, minus = mirrored on f-.
+// WENO5 takes 4 eps (its smoothness indicators are carried as 4 beta).
 template <class T, int ORDER>
 __device__ __forceinline__ T recon_plus(const T* w, T eps) {
-    if constexpr (ORDER == 5) return weno5<T>(w[0], w[1], w[2], w[3], w[4], eps);
+    if constexpr (ORDER == 5) return weno5<T>(w[0], w[1], w[2], w[3], w[4], (T)4 * eps);
     else return weno7<T>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], eps);
 }
 template <class T, int ORDER>
 __device__ __forceinline__ T recon_minus(const T* w, T eps) {
-    if constexpr (ORDER == 5) return weno5<T>(w[5], w[4], w[3], w[2], w[1], eps);
+    if constexpr (ORDER == 5) return weno5<T>(w[5], w[4], w[3], w[2], w[1], (T)4 * eps);
     else return weno7<T>(w[7], w[6], w[5], w[4], w[3], w[2], w[1], eps);
 }
 
@@ -164,26 +169,42 @@ __global__ void __launch_bounds__(256) sweep_x(SweepArgs<T> A) {
 // ---------------------------------------------------------------------------
 // y / z sweeps: per-lane rolling register window
 // ---------------------------------------------------------------------------
+// Load through a uniform base pointer and a 32-bit byte offset (the plan limits
+// one field to < 4 GiB), so that address arithmetic stays 32-bit per lane.
+template <class T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
+    return *(const T*)((const char*)base + off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
+    *(T*)((char*)base + off) = v;
+}
+
 template <class T, int ORDER, int DIR>
-__global__ void __launch_bounds__(256) sweep_roll(SweepArgs<T> A) {
+__device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R;
     constexpr int WD = DIR == 1 ? 2 : 1;   // the other transverse axis
-    const int nx = A.n[0];
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int w = blockIdx.y * 4 + threadIdx.y;
-    if (x >= nx || w >= A.n[WD]) return;
+    const int nx = A.n[0], nw = A.n[WD];
+    // lanes enumerate the (x, w) plane x-fastest, so a wave reads at most two
+    // contiguous runs of x per field whatever nx is
+    const unsigned p = blockIdx.x * 256u + threadIdx.x;
+    const int x = (int)(p % (unsigned)nx), w = (int)(p / (unsigned)nx);
+    if (w >= nw) return;
     const int nd = A.n[DIR];
-    const int k0 = blockIdx.z * A.seg;
+    const int k0 = blockIdx.y * A.seg;
     const int kend = min(k0 + A.seg, nd);
-    const long long stride = DIR == 1 ? (long long)nx : (long long)nx * A.n[1];
-    const long long base = DIR == 1 ? x + (long long)nx * A.n[1] * w : x + (long long)nx * w;
+    const uint32_t sb = (uint32_t)sizeof(T) * (DIR == 1 ? (uint32_t)nx : (uint32_t)nx * A.n[1]);
+    const uint32_t cb = (uint32_t)sizeof(T) *
+                        (DIR == 1 ? (uint32_t)x + (uint32_t)nx * A.n[1] * (uint32_t)w
+                                  : (uint32_t)x + (uint32_t)nx * (uint32_t)w);
+    const long long F = A.fstride;
     unsigned clamped = 0;
 
     auto fetch = [&](int m, T u[5]) {
         if (m >= 0 && m < nd) {
-            const long long id = base + m * stride;
+            const uint32_t off = cb + (uint32_t)m * sb;
 #pragma unroll
-            for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
+            for (int f = 0; f < 5; ++f) u[f] = ld_off(A.us + f * F, off);
         } else if (DIR == 1) {
             load_cell<T, DIR>(A, x, m, w, u);
         } else {
@@ -209,9 +230,27 @@ __global__ void __launch_bounds__(256) sweep_roll(SweepArgs<T> A) {
     for (int c = 0; c < 5; ++c)
         Fl[c] = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
 
+    T nxt[5];
+    fetch(k0 + R, nxt);
     for (int k = k0; k < kend; ++k) {
-        T u[5], fp[5], fm[5];
-        fetch(k + R, u);
+        T u[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f] = nxt[f];
+        fetch(k + 1 + R, nxt);   // next iteration's new cell, in flight during this one
+        // epilogue operands of cell k: FP32 issues them before the arithmetic;
+        // FP64 loads them after it to keep the register window within 256 VGPRs
+        const uint32_t off = cb + (uint32_t)k * sb;
+        T lo[5], us[5], u0[5];
+        auto load_epilogue = [&]() {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                lo[c] = A.first ? (T)0 : ld_off(A.lacc + c * F, off);
+                us[c] = A.stage != STAGE_WRITE_L ? ld_off(A.us + c * F, off) : (T)0;
+                u0[c] = A.stage >= STAGE_2 ? ld_off(A.u0 + c * F, off) : (T)0;
+            }
+        };
+        if constexpr (sizeof(T) == 4) load_epilogue();
+        T fp[5], fm[5];
         split_flux<T, DIR>(u, fp, fm, clamped);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -223,16 +262,56 @@ __global__ void __launch_bounds__(256) sweep_roll(SweepArgs<T> A) {
             wp[c][W - 1] = fp[c];
             wm[c][W - 1] = fm[c];
         }
-        T L[5];
+        T Lk[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             const T Fr = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
-            L[c] = (Fl[c] - Fr) * A.inv_h;
+            Lk[c] = (Fl[c] - Fr) * A.inv_h;
             Fl[c] = Fr;
         }
-        epilogue(A, base + k * stride, L);
+        if constexpr (sizeof(T) != 4) load_epilogue();
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            T L = Lk[c];
+            if (!A.first) L = lo[c] + L;
+            T v;
+            if (A.stage == STAGE_WRITE_L) {
+                v = L;
+            } else {
+                v = us[c] + A.dt * L;
+                if (A.stage == STAGE_2) v = (T)0.75 * u0[c] + (T)0.25 * v;
+                else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * u0[c] + (T)(2.0 / 3.0) * v;
+            }
+            st_off(A.stage == STAGE_WRITE_L ? A.lacc + c * F : A.uout + c * F, off, v);
+        }
     }
     if (clamped) atomicAdd(A.clamps, clamped);
+}
+
+// Minimum resident 256-thread blocks per CU for the rolling sweeps (= waves per
+// SIMD); caps the register window so that enough waves hide load latency.
+#ifndef RH_ROLL_MINB_F32_W5
+#define RH_ROLL_MINB_F32_W5 3
+#endif
+#ifndef RH_ROLL_MINB_F32_W7
+#define RH_ROLL_MINB_F32_W7 3
+#endif
+#ifndef RH_ROLL_MINB_F64_W5
+#define RH_ROLL_MINB_F64_W5 2
+#endif
+#ifndef RH_ROLL_MINB_F64_W7
+#define RH_ROLL_MINB_F64_W7 1
+#endif
+
+template <int ORDER, int DIR>
+__global__ void __launch_bounds__(256, ORDER == 5 ? RH_ROLL_MINB_F32_W5 : RH_ROLL_MINB_F32_W7)
+sweep_roll_f32(SweepArgs<float> A) {
+    sweep_roll_body<float, ORDER, DIR>(A);
+}
+template <int ORDER, int DIR>
+__global__ void __launch_bounds__(256, ORDER == 5 ? RH_ROLL_MINB_F64_W5 : RH_ROLL_MINB_F64_W7)
+sweep_roll_f64(SweepArgs<double> A) {
+    sweep_roll_body<double, ORDER, DIR>(A);
 }
 
 // Stage combine with L = 0 (grids with no axis longer than one cell).
@@ -403,6 +482,11 @@ int choose_tile_x(int nx, int ghosts) {
 }
 
 int choose_segment(int n, int ncol_lanes) {
+    static const int forced = [] {
+        const char* e = getenv("RH_ROLL_SEGMENT");
+        return e ? atoi(e) : 0;
+    }();
+    if (forced > 0) return forced < n ? forced : n;
     // enough lanes to fill the chip (about 2^19), segments no shorter than 32 cells
     const long long target = 1LL << 19;
     long long nseg = (target + ncol_lanes - 1) / ncol_lanes;
@@ -428,11 +512,13 @@ static hipError_t launch_x(const SweepArgs<T>& a, hipStream_t s) {
 template <class T, int ORDER, int DIR>
 static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
     const int wd = DIR == 1 ? 2 : 1;
-    const unsigned gx = (a.n[0] + 63) / 64, gy = (a.n[wd] + 3) / 4;
-    const int seg = choose_segment(a.n[DIR], (int)(gx * 64 * gy * 4));
+    const long long cols = (long long)a.n[0] * a.n[wd];
+    const unsigned gx = (unsigned)((cols + 255) / 256);
+    const int seg = choose_segment(a.n[DIR], (int)(gx * 256));
     a.seg = seg;
-    const unsigned gz = (a.n[DIR] + seg - 1) / seg;
-    sweep_roll<T, ORDER, DIR><<<dim3(gx, gy, gz), dim3(64, 4), 0, s>>>(a);
+    const unsigned gy = (a.n[DIR] + seg - 1) / seg;
+    if constexpr (sizeof(T) == 4) sweep_roll_f32<ORDER, DIR><<<dim3(gx, gy), dim3(256), 0, s>>>(a);
+    else sweep_roll_f64<ORDER, DIR><<<dim3(gx, gy), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }
 
