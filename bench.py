@@ -151,6 +151,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy three times (reference "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the path has no multi-GPU mode); "
@@ -160,6 +163,14 @@ def main():
     import torch
     from paper_1604_03360_amd import inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     spec = inputs.blob(n=args.n, order=args.scheme)
     ncell = args.n ** 3
     print("bench: blob %d^3 WENO%d, %d warmup + %d timed steps" % (args.n, args.scheme, args.warmup,
