@@ -163,6 +163,70 @@ rh_status rh_set_timing(rh_plan* plan, int enable);
  * (n <= RH_KERNEL_CLASSES).  Synchronises the stream. */
 rh_status rh_kernel_times(rh_plan* plan, double* ms_out, long long* launches_out, int n);
 
+/* ------------------------------------------------------------------------
+ * Event-by-event ensembles (batched grids).  The paper's motivation is
+ * event-by-event simulation of many independent collisions (abstract and
+ * Sec. 1 introduction); a batch advances many independent grids together with
+ * one launch per directional sweep per Runge-Kutta stage covering every grid.
+ * ------------------------------------------------------------------------ */
+typedef struct rh_batch rh_batch;
+
+/* Create a batch of n_grids independent grids.  All descriptions must share
+ * scheme and precision and have at least 2 cells on every axis (RH_E_NOTSUP
+ * otherwise).  Each grid's state occupies elements [offset_g, offset_g +
+ * 5*ncell_g) of one concatenated buffer, in the single-grid layout
+ * [5][nz][ny][nx]; offsets are multiples of 64 elements. */
+rh_status rh_batch_create(rh_batch** out, int n_grids, const rh_grid_desc* descs);
+
+/* Release a batch (library-owned memory only; NULL is ignored). */
+void rh_batch_destroy(rh_batch* batch);
+
+/* offsets[0 .. n_grids]: element offset of every grid's state in the
+ * concatenated buffer; offsets[n_grids] is the total element count. */
+rh_status rh_batch_offsets(const rh_batch* batch, long long* offsets);
+
+/* Bytes of the concatenated state, and of the workspace (3 such buffers). */
+size_t rh_batch_state_bytes(const rh_batch* batch);
+size_t rh_batch_workspace_bytes(const rh_batch* batch);
+
+/* Bind caller-owned device buffers (16-byte aligned) and a stream, as rh_bind. */
+rh_status rh_batch_bind(rh_batch* batch, void* state, void* workspace, void* stream);
+
+/* As rh_set_fields / rh_get_fields, on FP64 device buffers laid out with the
+ * batch offsets (total element count from rh_batch_offsets). */
+rh_status rh_batch_set_fields(rh_batch* batch, const double* src, int kind);
+rh_status rh_batch_get_fields(rh_batch* batch, double* dst, int kind);
+
+/* Advance every grid n_steps SSP-RK3 steps of size dt (Sec. 1).  Each stage is
+ * three launches (x, y, z sweeps), each covering all grids; with graphs
+ * enabled the nine launches of a step are captured once in a hipGraph and
+ * replayed.  Errors as rh_step. */
+rh_status rh_batch_step(rh_batch* batch, double dt, int n_steps, double* t_inout);
+
+/* Per-grid FP64 totals out[n_grids][5] (E, Mx, My, Mz, N) and counters as
+ * rh_totals.  Synchronises the stream. */
+rh_status rh_batch_totals(rh_batch* batch, double* out, long long counters[2]);
+
+/* Enable (nonzero) or disable hipGraph capture and replay of whole steps.
+ * Ignored (no graph) when any grid has a HUBBLE boundary, whose ghost values
+ * depend on the stage time. */
+rh_status rh_batch_set_graph(rh_batch* batch, int enable);
+
+/* Launch shape of the batched sweeps: x tile width (64, 32 or 16 cells) and
+ * the rolling segment lengths along y and z (>= 4 cells). */
+rh_status rh_batch_set_tuning(rh_batch* batch, int tile_x, int seg_y, int seg_z);
+rh_status rh_batch_get_tuning(const rh_batch* batch, int* tile_x, int* seg_y, int* seg_z);
+
+/* Time the candidate launch shapes on the bound state (evaluations of L into
+ * the workspace; the state is not modified) with HIP events, keep the fastest
+ * and report it through rh_batch_get_tuning.  reps >= 1 timed launches per
+ * candidate.  Synchronises the stream. */
+rh_status rh_batch_autotune(rh_batch* batch, int reps);
+
+/* Per-kernel timing of batched launches, as rh_set_timing / rh_kernel_times. */
+rh_status rh_batch_set_timing(rh_batch* batch, int enable);
+rh_status rh_batch_kernel_times(rh_batch* batch, double* ms_out, long long* launches_out, int n);
+
 #ifdef __cplusplus
 }
 #endif

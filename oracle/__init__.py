@@ -67,6 +67,9 @@ def lib():
         L.orc_jvp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
         L.orc_riemann_conformal.argtypes = [ctypes.c_double] * 4 + [ctypes.c_long, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_vjp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
+        L.orc_vjp_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.orc_jvp_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -203,3 +206,33 @@ def riemann_conformal(eL, nL, eR, nR, xi):
         raise ValueError("riemann_conformal expects eL > eR > 0")
     keys = ("e_star", "v_star", "n_left_star", "n_right_star", "v_shock", "xi_tail")
     return out, dict(zip(keys, star))
+
+
+def vjp_L(grid, u, w, t=0.0):
+    """J(u)^T w for the operator L at time t (hand-written adjoint)."""
+    u = _f64(u)
+    w = _f64(w)
+    out = np.empty_like(u)
+    rc = lib().orc_vjp_L(ctypes.byref(grid), float(t), _dp(u), _dp(w), _dp(out))
+    assert rc == 0
+    return out
+
+
+def vjp_step(grid, u, ubar, dt, t=0.0):
+    """Adjoint of one SSP-RK3 step from state u at time t."""
+    u = _f64(u)
+    ubar = _f64(ubar)
+    out = np.empty_like(u)
+    rc = lib().orc_vjp_step(ctypes.byref(grid), float(t), float(dt), _dp(u), _dp(ubar), _dp(out))
+    assert rc == 0
+    return out
+
+
+def jvp_step(grid, u, v, dt, t=0.0):
+    """Directional derivative of one SSP-RK3 step (complex step)."""
+    u = _f64(u)
+    v = _f64(v)
+    out = np.empty_like(u)
+    rc = lib().orc_jvp_step(ctypes.byref(grid), float(t), float(dt), _dp(u), _dp(v), _dp(out))
+    assert rc == 0
+    return out

@@ -314,9 +314,10 @@ void apply_L(const orc_grid& g, double t, const T* u, T* L, long* clamps) {
 }
 
 // Shu-Osher SSP-RK3 (Sec. 1, third-order Runge-Kutta), stage times t, t+dt, t+dt/2.
-void rk3_step(const orc_grid& g, double t, double dt, double* u, long* clamps) {
+template <class T>
+void rk3_step(const orc_grid& g, double t, double dt, T* u, long* clamps) {
     size_t N = 5 * (size_t)g.n[0] * g.n[1] * g.n[2];
-    std::vector<double> L(N), u1(N), u2(N);
+    std::vector<T> L(N), u1(N), u2(N);
     apply_L(g, t, u, L.data(), clamps);
     for (size_t q = 0; q < N; ++q) u1[q] = u[q] + dt * L[q];
     apply_L(g, t + dt, u1.data(), L.data(), clamps);
@@ -556,3 +557,234 @@ extern "C" int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+// ---------------------------------------------------------------------------
+// Adjoint (vector-Jacobian products) of L and of one SSP-RK3 step.
+//
+// With w a field of weights, sum_i w_i . L_i = sum over every interface i+1/2
+// of Fhat(i+1/2) . (w_{i+1} - w_i) / h (summation by parts of Eq. (2), with w
+// zero outside the grid).  Each face flux depends on the split fluxes of its
+// stencil cells, each split flux f+- = (F(u) +- u)/2 on the state of its cell,
+// and ghost cells are copies of interior cells (periodic, outflow) or
+// constants (analytic boundaries).  The chain rule is applied in that order:
+//   * d fhat / d s_j from the WENO formula: omega-weighted candidate
+//     coefficients plus the weight sensitivities,
+//     d fhat/d s_j = sum_k omega_k dq_k/ds_j
+//                    - 2 sum_k omega_k (q_k - fhat)/(eps + beta_k) dbeta_k/ds_j;
+//     the linear and quadratic forms q_k(s), beta_k(s) are read off the forward
+//     formulas at unit vectors (beta_k by polarization), so no coefficient is
+//     typed twice;
+//   * d F / d u per cell by the complex step of the forward flux (exact to
+//     rounding);
+//   * contributions to ghost cells are sent back to the interior cell they copy.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct WenoForms {
+    int r = 0;
+    double Q[4][7];       // q_k = sum_j Q[k][j] s_j
+    double B[4][7][7];    // beta_k = s^T B_k s (symmetric)
+};
+
+WenoForms weno_forms(int order) {
+    WenoForms F;
+    F.r = order == 5 ? 3 : 4;
+    const int m = 2 * F.r - 1;
+    double e[7], q[4], b[4];
+    double bd[7][4];
+    for (int j = 0; j < m; ++j) {
+        for (int i = 0; i < m; ++i) e[i] = i == j ? 1.0 : 0.0;
+        if (order == 5) weno5_parts(e, q, b); else weno7_parts(e, q, b);
+        for (int k = 0; k < F.r; ++k) {
+            F.Q[k][j] = q[k];
+            F.B[k][j][j] = b[k];
+            bd[j][k] = b[k];
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = i + 1; j < m; ++j) {
+            for (int t = 0; t < m; ++t) e[t] = (t == i || t == j) ? 1.0 : 0.0;
+            if (order == 5) weno5_parts(e, q, b); else weno7_parts(e, q, b);
+            for (int k = 0; k < F.r; ++k) {
+                const double off = 0.5 * (b[k] - bd[i][k] - bd[j][k]);
+                F.B[k][i][j] = off;
+                F.B[k][j][i] = off;
+            }
+        }
+    return F;
+}
+
+const WenoForms& forms(int order) {
+    static const WenoForms f5 = weno_forms(5), f7 = weno_forms(7);
+    return order == 5 ? f5 : f7;
+}
+
+// gradient of the left-biased reconstruction with respect to its 2r-1 inputs
+void weno_grad(int order, const double* s, double eps, double* grad) {
+    const WenoForms& F = forms(order);
+    const int r = F.r, m = 2 * r - 1;
+    const double* d = order == 5 ? D5 : D7;
+    double q[4], b[4];
+    if (order == 5) weno5_parts(s, q, b); else weno7_parts(s, q, b);
+    double alpha[4], sum = 0.0;
+    for (int k = 0; k < r; ++k) {
+        const double gk = eps + b[k];
+        alpha[k] = d[k] / (gk * gk);
+        sum += alpha[k];
+    }
+    double omega[4], fhat = 0.0;
+    for (int k = 0; k < r; ++k) {
+        omega[k] = alpha[k] / sum;
+        fhat += omega[k] * q[k];
+    }
+    for (int j = 0; j < m; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < r; ++k) {
+            double dbeta = 0.0;
+            for (int i = 0; i < m; ++i) dbeta += 2.0 * F.B[k][j][i] * s[i];
+            acc += omega[k] * F.Q[k][j] - 2.0 * omega[k] * (q[k] - fhat) / (eps + b[k]) * dbeta;
+        }
+        grad[j] = acc;
+    }
+}
+
+// J[c][q] = d F_{d,c} / d u_q for one cell (complex step of the forward flux)
+void flux_jacobian(int d, const double u[5], double J[5][5]) {
+    const double h = 1e-30;
+    for (int q = 0; q < 5; ++q) {
+        cplx uc[5], v[3], p, nd, f[5];
+        for (int c = 0; c < 5; ++c) uc[c] = cplx(u[c], c == q ? h : 0.0);
+        con2prim(uc, v, p, nd, (long*)nullptr);
+        flux(d, uc, v, p, f);
+        for (int c = 0; c < 5; ++c) J[c][q] = f[c].imag() / h;
+    }
+}
+
+// interior index of line position m along axis d (or -1 for analytic ghosts)
+long line_target(const orc_grid& g, int d, const int ijk[3], int m) {
+    const int nd = g.n[d];
+    int c[3] = {ijk[0], ijk[1], ijk[2]};
+    if (m >= 0 && m < nd) c[d] = m;
+    else if (g.bc[d] == BC_PERIODIC) c[d] = ((m % nd) + nd) % nd;
+    else if (g.bc[d] == BC_OUTFLOW) c[d] = m < 0 ? 0 : nd - 1;
+    else return -1;
+    return (long)cidx(g, c[0], c[1], c[2]);
+}
+
+// ubar += J(u)^T w at time t
+void vjp_L(const orc_grid& g, double t, const double* u, const double* w, double* ubar) {
+    const int r = g.order == 5 ? 3 : 4, G = r, m = 2 * r - 1;
+    const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+    for (int d = 0; d < 3; ++d) {
+        const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        const int nd = g.n[d];
+        const long nlines = (long)g.n[a1] * g.n[a2];
+        // lines are independent except for periodic wrap onto themselves, so a
+        // line's scatter stays inside the line: parallel over lines is safe
+#pragma omp parallel for schedule(static)
+        for (long line = 0; line < nlines; ++line) {
+            int ijk[3];
+            ijk[d] = 0;
+            ijk[a1] = (int)(line % g.n[a1]);
+            ijk[a2] = (int)(line / g.n[a1]);
+            const int len = nd + 2 * G;
+            std::vector<double> uc(5 * len), fp(5 * len), fm(5 * len), ap(5 * len, 0.0), am(5 * len, 0.0);
+            for (int mm = -G; mm < nd + G; ++mm) {
+                double ul[5], v[3], p, nden, f[5];
+                line_cell(g, t, u, d, ijk, mm, ul);
+                con2prim(ul, v, p, nden, (long*)nullptr);
+                flux(d, ul, v, p, f);
+                for (int c = 0; c < 5; ++c) {
+                    uc[c * len + mm + G] = ul[c];
+                    fp[c * len + mm + G] = 0.5 * (f[c] + ul[c]);
+                    fm[c * len + mm + G] = 0.5 * (f[c] - ul[c]);
+                }
+            }
+            for (int i = -1; i < nd; ++i) {
+                for (int c = 0; c < 5; ++c) {
+                    const double wr = i + 1 < nd ? w[c * ncell + line_target(g, d, ijk, i + 1)] : 0.0;
+                    const double wl = i >= 0 ? w[c * ncell + line_target(g, d, ijk, i)] : 0.0;
+                    const double gi = (wr - wl) / g.h[d];
+                    double sp[7], sm[7], gp[7], gm[7];
+                    for (int o = 0; o < m; ++o) {
+                        sp[o] = fp[c * len + (i - r + 1 + o) + G];
+                        sm[o] = fm[c * len + (i + r - o) + G];
+                    }
+                    weno_grad(g.order, sp, g.eps, gp);
+                    weno_grad(g.order, sm, g.eps, gm);
+                    for (int o = 0; o < m; ++o) {
+                        ap[c * len + (i - r + 1 + o) + G] += gi * gp[o];
+                        am[c * len + (i + r - o) + G] += gi * gm[o];
+                    }
+                }
+            }
+            for (int mm = -G; mm < nd + G; ++mm) {
+                const long tgt = line_target(g, d, ijk, mm);
+                if (tgt < 0) continue;
+                double ul[5], J[5][5];
+                for (int c = 0; c < 5; ++c) ul[c] = uc[c * len + mm + G];
+                flux_jacobian(d, ul, J);
+                for (int q = 0; q < 5; ++q) {
+                    double acc = 0.5 * (ap[q * len + mm + G] - am[q * len + mm + G]);
+                    for (int c = 0; c < 5; ++c)
+                        acc += 0.5 * (ap[c * len + mm + G] + am[c * len + mm + G]) * J[c][q];
+                    ubar[q * ncell + tgt] += acc;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+// out = J(u)^T w for L at time t (fields [5][nz][ny][nx]).
+int orc_vjp_L(const orc_grid* g, double t, const double* u, const double* w, double* out) {
+    if (!grid_ok(g)) return -1;
+    const size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
+    for (size_t q = 0; q < N; ++q) out[q] = 0.0;
+    vjp_L(*g, t, u, w, out);
+    return 0;
+}
+
+// Adjoint of one SSP-RK3 step from u (time t): ubar_out = (d u_{n+1} / d u_n)^T ubar_in.
+// Stage states are recomputed; the stage adjoints are
+//   b2 = 2/3 b3 + 2/3 dt J(u2)^T b3,  b1 = 1/4 b2 + 1/4 dt J(u1)^T b2,
+//   b0 = 1/3 b3 + 3/4 b2 + b1 + dt J(u)^T b1,  with b3 = ubar_in.
+int orc_vjp_step(const orc_grid* g, double t, double dt, const double* u, const double* ubar_in,
+                 double* ubar_out) {
+    if (!grid_ok(g)) return -1;
+    const size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
+    std::vector<double> L(N), u1(N), u2(N), b2(N), b1(N), tmp(N);
+    apply_L(*g, t, u, L.data(), (long*)nullptr);
+    for (size_t q = 0; q < N; ++q) u1[q] = u[q] + dt * L[q];
+    apply_L(*g, t + dt, u1.data(), L.data(), (long*)nullptr);
+    for (size_t q = 0; q < N; ++q) u2[q] = 0.75 * u[q] + 0.25 * (u1[q] + dt * L[q]);
+    std::fill(tmp.begin(), tmp.end(), 0.0);
+    vjp_L(*g, t + 0.5 * dt, u2.data(), ubar_in, tmp.data());
+    for (size_t q = 0; q < N; ++q) b2[q] = (2.0 / 3.0) * ubar_in[q] + (2.0 / 3.0) * dt * tmp[q];
+    std::fill(tmp.begin(), tmp.end(), 0.0);
+    vjp_L(*g, t + dt, u1.data(), b2.data(), tmp.data());
+    for (size_t q = 0; q < N; ++q) b1[q] = 0.25 * b2[q] + 0.25 * dt * tmp[q];
+    std::fill(tmp.begin(), tmp.end(), 0.0);
+    vjp_L(*g, t, u, b1.data(), tmp.data());
+    for (size_t q = 0; q < N; ++q)
+        ubar_out[q] = (1.0 / 3.0) * ubar_in[q] + 0.75 * b2[q] + b1[q] + dt * tmp[q];
+    return 0;
+}
+
+// Directional derivative of one SSP-RK3 step by the complex step.
+int orc_jvp_step(const orc_grid* g, double t, double dt, const double* u, const double* v,
+                 double* jv) {
+    if (!grid_ok(g)) return -1;
+    const double h = 1e-30;
+    const size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
+    std::vector<cplx> uc(N);
+    for (size_t q = 0; q < N; ++q) uc[q] = cplx(u[q], h * v[q]);
+    rk3_step(*g, t, dt, uc.data(), (long*)nullptr);
+    for (size_t q = 0; q < N; ++q) jv[q] = uc[q].imag() / h;
+    return 0;
+}
+
+}  // extern "C"

@@ -377,3 +377,549 @@ rh_status rh_kernel_times(rh_plan* p, double* ms_out, long long* launches_out, i
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Event-by-event batches
+// ===========================================================================
+struct rh_batch {
+    std::vector<rh_grid_desc> d;
+    std::vector<long long> off;     // ngrid + 1 element offsets
+    int ngrid = 0;
+    int scheme = 5;
+    int precision = RH_PREC_FP64;
+    size_t elem = 8;
+    bool any_hubble = false;
+    // launch shape
+    int tile_x = 32, seg[3] = {0, 32, 32};
+    int nblocks[3] = {0, 0, 0};
+    void* d_grids = nullptr;         // BatchGrid<T>[ngrid]
+    // binding
+    void* state = nullptr;
+    void* ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    unsigned* d_clamps = nullptr;
+    double* d_partials = nullptr;
+    double* d_totals = nullptr;      // [ngrid][6]
+    // graphs
+    bool graph_on = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_dt = 0.0;
+    const void* graph_state = nullptr;
+    const void* graph_ws = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+    size_t event_next = 0;
+};
+
+namespace {
+
+void drop_graph(rh_batch* b) {
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+}
+
+template <class T>
+rh_status upload_batch_table(rh_batch* b) {
+    std::vector<rh::BatchGrid<T>> g(b->ngrid);
+    int acc[3] = {0, 0, 0};
+    for (int i = 0; i < b->ngrid; ++i) {
+        const rh_grid_desc& d = b->d[i];
+        rh::BatchGrid<T>& G = g[i];
+        std::memset(&G, 0, sizeof(G));
+        G.off = b->off[i];
+        G.n[0] = d.nx;
+        G.n[1] = d.ny;
+        G.n[2] = d.nz;
+        const double h[3] = {d.dx, d.dy, d.dz};
+        const double c0[3] = {d.x0, d.y0, d.z0};
+        for (int a = 0; a < 3; ++a) {
+            G.bc[a] = d.bc[a];
+            G.inv_h[a] = (T)(1.0 / h[a]);
+            G.h[a] = h[a];
+            G.c0[a] = c0[a];
+            G.seg[a] = b->seg[a] > 0 ? (b->seg[a] < G.n[a] ? b->seg[a] : G.n[a]) : 1;
+        }
+        int blocks[3];
+        rh::batch_blocks(G.n, b->tile_x, G.seg, blocks, G.nchunk);
+        for (int c = 0; c < 3; ++c) {
+            G.blk0[c] = acc[c];
+            acc[c] += blocks[c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) b->nblocks[c] = acc[c];
+    if (!b->d_grids) {
+        hipError_t e = hipMalloc(&b->d_grids, g.size() * sizeof(rh::BatchGrid<T>));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    }
+    hipError_t e = hipMemcpy(b->d_grids, g.data(), g.size() * sizeof(rh::BatchGrid<T>),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    drop_graph(b);
+    return RH_OK;
+}
+
+rh_status upload_table(rh_batch* b) {
+    return b->precision == RH_PREC_FP32 ? upload_batch_table<float>(b) : upload_batch_table<double>(b);
+}
+
+template <class F>
+rh_status batch_timed(rh_batch* b, hipStream_t s, int cls, F&& launch, const char* what) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->timing) {
+        for (hipEvent_t* e : {&e0, &e1}) {
+            if (b->event_next == b->event_pool.size()) {
+                hipEvent_t ev;
+                if (hipEventCreate(&ev) != hipSuccess) return fail(RH_E_HIP, "hipEventCreate failed");
+                b->event_pool.push_back(ev);
+            }
+            *e = b->event_pool[b->event_next++];
+        }
+        hipError_t er = hipEventRecord(e0, s);
+        if (er != hipSuccess) return hip_fail(er, "hipEventRecord");
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (b->timing) {
+        hipError_t er = hipEventRecord(e1, s);
+        if (er != hipSuccess) return hip_fail(er, "hipEventRecord");
+        b->timed.push_back({cls, e0, e1});
+    }
+    return RH_OK;
+}
+
+// One evaluation of L for every grid: three launches (x, y, z), the last one
+// fusing the stage combine (stage > 0) or storing L (stage == 0).
+template <class T>
+rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T* lacc, T* uout,
+                         double t, double dt, int stage) {
+    rh::BatchArgs<T> B;
+    std::memset(&B, 0, sizeof(B));
+    B.grids = (const rh::BatchGrid<T>*)b->d_grids;
+    B.ngrid = b->ngrid;
+    B.base.us = us;
+    B.base.u0 = u0;
+    B.base.lacc = lacc;
+    B.base.uout = uout;
+    B.base.dt = (T)dt;
+    B.base.eps = (T)(b->d[0].weno_eps > 0.0 ? b->d[0].weno_eps : 1e-6);
+    B.base.hb.t = t;
+    B.base.hb.t0 = b->d[0].hubble_t0;
+    B.base.hb.e0 = b->d[0].hubble_e0;
+    B.base.hb.n0 = b->d[0].hubble_n0;
+    B.base.clamps = b->d_clamps;
+    for (int d = 0; d < 3; ++d) {
+        rh::BatchArgs<T> Bd = B;
+        Bd.base.first = d == 0;
+        Bd.base.stage = d == 2 ? stage : rh::STAGE_WRITE_L;
+        rh_status st = batch_timed(b, s, RH_KERNEL_SWEEP_X + d, [&] {
+            return rh::launch_sweep_batch<T>(d, b->scheme, b->tile_x, Bd, b->nblocks[d], s);
+        }, "batched sweep launch");
+        if (st != RH_OK) return st;
+    }
+    return RH_OK;
+}
+
+template <class T>
+rh_status batch_one_step(rh_batch* b, hipStream_t s, double t, double dt) {
+    const size_t S = (size_t)b->off[b->ngrid];
+    T* U0 = (T*)b->state;
+    T* U1 = (T*)b->ws;
+    T* U2 = U1 + S;
+    T* Lc = U2 + S;
+    rh_status st = batch_evaluate<T>(b, s, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
+    if (st == RH_OK) st = batch_evaluate<T>(b, s, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2);
+    if (st == RH_OK) st = batch_evaluate<T>(b, s, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3);
+    return st;
+}
+
+template <class T>
+rh_status batch_step_impl(rh_batch* b, double dt, int nsteps, double t) {
+    const bool use_graph = b->graph_on && !b->any_hubble && !b->timing;
+    if (!use_graph) {
+        for (int k = 0; k < nsteps; ++k) {
+            rh_status st = batch_one_step<T>(b, b->stream, t, dt);
+            if (st != RH_OK) return st;
+            t += dt;
+        }
+        return RH_OK;
+    }
+    if (!b->graph_exec || b->graph_dt != dt || b->graph_state != b->state || b->graph_ws != b->ws) {
+        drop_graph(b);
+        hipError_t e;
+        if (!b->cap_stream &&
+            (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        rh_status st = batch_one_step<T>(b, b->cap_stream, t, dt);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != RH_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        if ((e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            drop_graph(b);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        b->graph_dt = dt;
+        b->graph_state = b->state;
+        b->graph_ws = b->ws;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        hipError_t e = hipGraphLaunch(b->graph_exec, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    return RH_OK;
+}
+
+rh_status check_batch(const rh_batch* b) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (!b->bound) return fail(RH_E_STATE, "batch has no bound state/workspace (call rh_batch_bind)");
+    return RH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rh_status rh_batch_create(rh_batch** out, int n_grids, const rh_grid_desc* descs) {
+    if (!out) return fail(RH_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n_grids < 1 || !descs) return fail(RH_E_INVAL, "need at least one grid description");
+    rh_batch* b = new (std::nothrow) rh_batch();
+    if (!b) return fail(RH_E_NOMEM, "host allocation failed");
+    b->ngrid = n_grids;
+    b->scheme = descs[0].scheme;
+    b->precision = descs[0].precision;
+    b->elem = b->precision == RH_PREC_FP32 ? 4 : 8;
+    b->off.assign(n_grids + 1, 0);
+    long long acc = 0;
+    for (int i = 0; i < n_grids; ++i) {
+        const rh_grid_desc& d = descs[i];
+        // validate each description exactly as a single-grid plan would
+        rh_plan* probe = nullptr;
+        rh_status st = rh_plan_create(&probe, &d);
+        if (st != RH_OK) {
+            delete b;
+            return st;
+        }
+        rh_plan_destroy(probe);
+        if (d.scheme != b->scheme || d.precision != b->precision) {
+            delete b;
+            return fail(RH_E_INVAL, "all grids of a batch must share scheme and precision");
+        }
+        if (d.nx < 2 || d.ny < 2 || d.nz < 2) {
+            delete b;
+            return fail(RH_E_NOTSUP, "batched grids need at least 2 cells on every axis");
+        }
+        for (int a = 0; a < 3; ++a)
+            if (d.bc[a] == RH_BC_HUBBLE) b->any_hubble = true;
+        b->d.push_back(d);
+        b->off[i] = acc;
+        const long long n = 5LL * d.nx * d.ny * d.nz;
+        acc += (n + 63) / 64 * 64;
+    }
+    b->off[n_grids] = acc;
+    // default launch shape: the x tile that stages the fewest cells over the
+    // whole ensemble, 32-cell rolling segments
+    long long best = -1;
+    for (int tx : {64, 32, 16}) {
+        long long staged = 0;
+        for (const rh_grid_desc& d : b->d)
+            staged += (long long)((d.nx + tx - 1) / tx) * (tx + 2 * ((b->scheme + 1) / 2)) * d.ny * d.nz;
+        if (best < 0 || staged < best) {
+            best = staged;
+            b->tile_x = tx;
+        }
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&b->d_clamps, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMalloc(&b->d_partials, 6 * rh::kTotalsBlocks * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&b->d_totals, 6 * (size_t)n_grids * sizeof(double))) != hipSuccess ||
+        (e = hipMemset(b->d_clamps, 0, sizeof(unsigned))) != hipSuccess) {
+        rh_batch_destroy(b);
+        return e == hipErrorOutOfMemory ? fail(RH_E_NOMEM, "hipMalloc failed") : hip_fail(e, "hipMalloc");
+    }
+    rh_status st = upload_table(b);
+    if (st != RH_OK) {
+        rh_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return RH_OK;
+}
+
+void rh_batch_destroy(rh_batch* b) {
+    if (!b) return;
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_grids) (void)hipFree(b->d_grids);
+    if (b->d_clamps) (void)hipFree(b->d_clamps);
+    if (b->d_partials) (void)hipFree(b->d_partials);
+    if (b->d_totals) (void)hipFree(b->d_totals);
+    for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
+    delete b;
+}
+
+rh_status rh_batch_offsets(const rh_batch* b, long long* offsets) {
+    if (!b || !offsets) return fail(RH_E_INVAL, "NULL argument");
+    for (int i = 0; i <= b->ngrid; ++i) offsets[i] = b->off[i];
+    return RH_OK;
+}
+
+size_t rh_batch_state_bytes(const rh_batch* b) { return b ? (size_t)b->off[b->ngrid] * b->elem : 0; }
+
+size_t rh_batch_workspace_bytes(const rh_batch* b) { return b ? 3 * rh_batch_state_bytes(b) : 0; }
+
+rh_status rh_batch_bind(rh_batch* b, void* state, void* workspace, void* stream) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (!state || !workspace) return fail(RH_E_INVAL, "state and workspace must be non-NULL");
+    if (((uintptr_t)state | (uintptr_t)workspace) & 15)
+        return fail(RH_E_INVAL, "buffers must be 16-byte aligned");
+    b->state = state;
+    b->ws = workspace;
+    b->stream = (hipStream_t)stream;
+    b->bound = true;
+    return RH_OK;
+}
+
+rh_status rh_batch_set_fields(rh_batch* b, const double* src, int kind) {
+    rh_status st = check_batch(b);
+    if (st != RH_OK) return st;
+    if (!src) return fail(RH_E_INVAL, "src is NULL");
+    if (kind != RH_FIELDS_CONSERVED && kind != RH_FIELDS_PRIMITIVE) return fail(RH_E_INVAL, "bad kind");
+    for (int i = 0; i < b->ngrid; ++i) {
+        const long long n = (long long)b->d[i].nx * b->d[i].ny * b->d[i].nz;
+        hipError_t e = b->precision == RH_PREC_FP32
+            ? rh::launch_set_fields<float>((float*)b->state + b->off[i], src + b->off[i], kind, n, b->stream)
+            : rh::launch_set_fields<double>((double*)b->state + b->off[i], src + b->off[i], kind, n, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "set_fields launch");
+    }
+    return RH_OK;
+}
+
+rh_status rh_batch_get_fields(rh_batch* b, double* dst, int kind) {
+    rh_status st = check_batch(b);
+    if (st != RH_OK) return st;
+    if (!dst) return fail(RH_E_INVAL, "dst is NULL");
+    if (kind != RH_FIELDS_CONSERVED && kind != RH_FIELDS_PRIMITIVE) return fail(RH_E_INVAL, "bad kind");
+    for (int i = 0; i < b->ngrid; ++i) {
+        const long long n = (long long)b->d[i].nx * b->d[i].ny * b->d[i].nz;
+        hipError_t e = b->precision == RH_PREC_FP32
+            ? rh::launch_get_fields<float>((const float*)b->state + b->off[i], dst + b->off[i], kind, n,
+                                           b->d_clamps, b->stream)
+            : rh::launch_get_fields<double>((const double*)b->state + b->off[i], dst + b->off[i], kind, n,
+                                            b->d_clamps, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "get_fields launch");
+    }
+    return RH_OK;
+}
+
+rh_status rh_batch_step(rh_batch* b, double dt, int n_steps, double* t_inout) {
+    rh_status st = check_batch(b);
+    if (st != RH_OK) return st;
+    if (!t_inout) return fail(RH_E_INVAL, "t_inout is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
+    if (n_steps < 0) return fail(RH_E_INVAL, "n_steps must be >= 0");
+    st = b->precision == RH_PREC_FP32 ? batch_step_impl<float>(b, dt, n_steps, *t_inout)
+                                      : batch_step_impl<double>(b, dt, n_steps, *t_inout);
+    if (st == RH_OK) *t_inout += n_steps * dt;
+    return st;
+}
+
+rh_status rh_batch_totals(rh_batch* b, double* out, long long counters[2]) {
+    rh_status st = check_batch(b);
+    if (st != RH_OK) return st;
+    if (!out) return fail(RH_E_INVAL, "out is NULL");
+    for (int i = 0; i < b->ngrid; ++i) {
+        const long long n = (long long)b->d[i].nx * b->d[i].ny * b->d[i].nz;
+        hipError_t e = b->precision == RH_PREC_FP32
+            ? rh::launch_totals<float>((const float*)b->state + b->off[i], n, b->d_partials,
+                                       rh::kTotalsBlocks, b->d_totals + 6 * i, b->stream)
+            : rh::launch_totals<double>((const double*)b->state + b->off[i], n, b->d_partials,
+                                        rh::kTotalsBlocks, b->d_totals + 6 * i, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "totals launch");
+    }
+    std::vector<double> host(6 * (size_t)b->ngrid);
+    unsigned clamps = 0;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(host.data(), b->d_totals, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            b->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(&clamps, b->d_clamps, sizeof(unsigned), hipMemcpyDeviceToHost, b->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    double bad = 0.0;
+    for (int i = 0; i < b->ngrid; ++i) {
+        for (int f = 0; f < 5; ++f) out[5 * i + f] = host[6 * i + f];
+        bad += host[6 * i + 5];
+    }
+    if (counters) {
+        counters[0] = clamps;
+        counters[1] = (long long)bad;
+    }
+    bool strict = false;
+    for (const rh_grid_desc& d : b->d) strict |= d.strict != 0;
+    if (strict && (clamps > 0 || bad > 0.0))
+        return fail(RH_E_PHYS, "strict batch: a primitive-recovery floor acted or a value is not finite");
+    return RH_OK;
+}
+
+rh_status rh_batch_set_graph(rh_batch* b, int enable) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    b->graph_on = enable != 0;
+    if (!b->graph_on) drop_graph(b);
+    return RH_OK;
+}
+
+rh_status rh_batch_set_tuning(rh_batch* b, int tile_x, int seg_y, int seg_z) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (tile_x != 64 && tile_x != 32 && tile_x != 16) return fail(RH_E_INVAL, "tile_x must be 64, 32 or 16");
+    if (seg_y < 4 || seg_z < 4) return fail(RH_E_INVAL, "segments must be >= 4 cells");
+    b->tile_x = tile_x;
+    b->seg[1] = seg_y;
+    b->seg[2] = seg_z;
+    return upload_table(b);
+}
+
+rh_status rh_batch_get_tuning(const rh_batch* b, int* tile_x, int* seg_y, int* seg_z) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (tile_x) *tile_x = b->tile_x;
+    if (seg_y) *seg_y = b->seg[1];
+    if (seg_z) *seg_z = b->seg[2];
+    return RH_OK;
+}
+
+rh_status rh_batch_autotune(rh_batch* b, int reps) {
+    rh_status st = check_batch(b);
+    if (st != RH_OK) return st;
+    if (reps < 1) return fail(RH_E_INVAL, "reps must be >= 1");
+    hipError_t e;
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const bool saved_timing = b->timing;
+    b->timing = false;
+    const size_t S = (size_t)b->off[b->ngrid];
+    // time one sweep class (evaluations of L into the workspace's accumulator)
+    auto time_class = [&](int cls, float* ms) -> rh_status {
+        auto one = [&]() -> rh_status {
+            if (b->precision == RH_PREC_FP32) {
+                float* L = (float*)b->ws + 2 * S;
+                rh::BatchArgs<float> B;
+                std::memset(&B, 0, sizeof(B));
+                B.grids = (const rh::BatchGrid<float>*)b->d_grids;
+                B.ngrid = b->ngrid;
+                B.base.us = (const float*)b->state;
+                B.base.u0 = (const float*)b->state;
+                B.base.lacc = L;
+                B.base.eps = (float)(b->d[0].weno_eps > 0.0 ? b->d[0].weno_eps : 1e-6);
+                B.base.clamps = b->d_clamps;
+                B.base.first = 1;
+                B.base.stage = rh::STAGE_WRITE_L;
+                hipError_t er = rh::launch_sweep_batch<float>(cls, b->scheme, b->tile_x, B, b->nblocks[cls], b->stream);
+                return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
+            }
+            double* L = (double*)b->ws + 2 * S;
+            rh::BatchArgs<double> B;
+            std::memset(&B, 0, sizeof(B));
+            B.grids = (const rh::BatchGrid<double>*)b->d_grids;
+            B.ngrid = b->ngrid;
+            B.base.us = (const double*)b->state;
+            B.base.u0 = (const double*)b->state;
+            B.base.lacc = L;
+            B.base.eps = b->d[0].weno_eps > 0.0 ? b->d[0].weno_eps : 1e-6;
+            B.base.clamps = b->d_clamps;
+            B.base.first = 1;
+            B.base.stage = rh::STAGE_WRITE_L;
+            hipError_t er = rh::launch_sweep_batch<double>(cls, b->scheme, b->tile_x, B, b->nblocks[cls], b->stream);
+            return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
+        };
+        rh_status s2 = one();   // warm-up
+        if (s2 != RH_OK) return s2;
+        if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        for (int r = 0; r < reps; ++r)
+            if ((s2 = one()) != RH_OK) return s2;
+        if ((e = hipEventRecord(e1, b->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        if ((e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        return RH_OK;
+    };
+    int best_tx = b->tile_x, best_seg[3] = {0, b->seg[1], b->seg[2]};
+    float best_ms = 1e30f;
+    rh_status rs = RH_OK;
+    for (int tx : {64, 32, 16}) {
+        b->tile_x = tx;
+        if ((rs = upload_table(b)) != RH_OK) break;
+        float ms;
+        if ((rs = time_class(0, &ms)) != RH_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_tx = tx;
+        }
+    }
+    b->tile_x = best_tx;
+    for (int d = 1; d < 3 && rs == RH_OK; ++d) {
+        best_ms = 1e30f;
+        for (int sg : {16, 32, 48, 64, 128}) {
+            b->seg[d] = sg;
+            if ((rs = upload_table(b)) != RH_OK) break;
+            float ms;
+            if ((rs = time_class(d, &ms)) != RH_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_seg[d] = sg;
+            }
+        }
+        b->seg[d] = best_seg[d];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->timing = saved_timing;
+    rh_status up = upload_table(b);
+    return rs != RH_OK ? rs : up;
+}
+
+rh_status rh_batch_set_timing(rh_batch* b, int enable) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (b->bound) (void)hipStreamSynchronize(b->stream);
+    b->timing = enable != 0;
+    b->timed.clear();
+    b->event_next = 0;
+    return RH_OK;
+}
+
+rh_status rh_batch_kernel_times(rh_batch* b, double* ms_out, long long* launches_out, int n) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (n < 0 || n > RH_KERNEL_CLASSES) return fail(RH_E_INVAL, "n out of range");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::vector<double> ms(RH_KERNEL_CLASSES, 0.0);
+    std::vector<long long> cnt(RH_KERNEL_CLASSES, 0);
+    for (const TimedLaunch& t : b->timed) {
+        float v = 0.f;
+        if ((e = hipEventElapsedTime(&v, t.a, t.b)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        ms[t.cls] += v;
+        cnt[t.cls] += 1;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (ms_out) ms_out[i] = ms[i];
+        if (launches_out) launches_out[i] = cnt[i];
+    }
+    return RH_OK;
+}
+
+}  // extern "C"

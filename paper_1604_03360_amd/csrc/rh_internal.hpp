@@ -31,11 +31,37 @@ struct SweepArgs {
     unsigned* clamps;   // floor counter
 };
 
+// One grid of a batched (event-ensemble) launch.  All of the grid's fields live
+// at element offset `off` of every batched buffer, in the single-grid layout.
+template <class T>
+struct BatchGrid {
+    long long off;
+    int n[3];
+    int bc[3];
+    T inv_h[3];
+    int blk0[3];     // first block of this grid in the launch of sweep class 0/1/2
+    int seg[3];      // rolling segment length along y (1) and z (2)
+    int nchunk[3];   // 256-lane chunks of the (x, w) plane for y (1) and z (2)
+    double c0[3];
+    double h[3];
+};
+
+template <class T>
+struct BatchArgs {
+    SweepArgs<T> base;            // buffers (batch bases), eps, dt, stage, first, time
+    const BatchGrid<T>* grids;    // device array
+    int ngrid;
+};
+
 // Launchers (return hipGetLastError() of the launch).
 template <class T>
 hipError_t launch_sweep(int dir, int order, const SweepArgs<T>& a, hipStream_t s);
 template <class T>
 hipError_t launch_combine(const SweepArgs<T>& a, hipStream_t s);
+template <class T>
+hipError_t launch_sweep_batch(int dir, int order, int tx, const BatchArgs<T>& b, int nblocks,
+                              hipStream_t s);
+void batch_blocks(const int n[3], int tx, const int seg[3], int blocks[3], int nchunk[3]);
 template <class T>
 hipError_t launch_set_fields(T* state, const double* src, int kind, long long ncell, hipStream_t s);
 template <class T>

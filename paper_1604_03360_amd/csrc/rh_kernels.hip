@@ -93,15 +93,16 @@ __device__ __forceinline__ void epilogue(const SweepArgs<T>& A, long long id, T 
 // ---------------------------------------------------------------------------
 // x sweep: LDS tile
 // ---------------------------------------------------------------------------
+// blk: linear block index within the grid (x tile fastest, then row tile)
 template <class T, int ORDER, int TX>
-__global__ void __launch_bounds__(256) sweep_x(SweepArgs<T> A) {
+__device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
     constexpr int R = (ORDER + 1) / 2, G = R, TY = 256 / TX, PW = TX + 2 * G;
     __shared__ T sp[5 * TY * PW];
     __shared__ T sm[5 * TY * PW];
     const int nx = A.n[0], ny = A.n[1];
     const int nrows = ny * A.n[2];
     const int ntx = (nx + TX - 1) / TX;
-    const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+    const int bx = blk % ntx, by = blk / ntx;
     const int x0 = bx * TX, r0 = by * TY;
     const int tid = threadIdx.x;
     unsigned clamped = 0;
@@ -180,18 +181,19 @@ __device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
     *(T*)((char*)base + off) = v;
 }
 
+// bx: 256-lane chunk of the (x, w) plane; by: segment along the sweep axis
 template <class T, int ORDER, int DIR>
-__device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A) {
+__device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned bx, int by) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R;
     constexpr int WD = DIR == 1 ? 2 : 1;   // the other transverse axis
     const int nx = A.n[0], nw = A.n[WD];
     // lanes enumerate the (x, w) plane x-fastest, so a wave reads at most two
     // contiguous runs of x per field whatever nx is
-    const unsigned p = blockIdx.x * 256u + threadIdx.x;
+    const unsigned p = bx * 256u + threadIdx.x;
     const int x = (int)(p % (unsigned)nx), w = (int)(p / (unsigned)nx);
     if (w >= nw) return;
     const int nd = A.n[DIR];
-    const int k0 = blockIdx.y * A.seg;
+    const int k0 = by * A.seg;
     const int kend = min(k0 + A.seg, nd);
     const uint32_t sb = (uint32_t)sizeof(T) * (DIR == 1 ? (uint32_t)nx : (uint32_t)nx * A.n[1]);
     const uint32_t cb = (uint32_t)sizeof(T) *
@@ -303,15 +305,76 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A) {
 #define RH_ROLL_MINB_F64_W7 1
 #endif
 
-template <int ORDER, int DIR>
-__global__ void __launch_bounds__(256, ORDER == 5 ? RH_ROLL_MINB_F32_W5 : RH_ROLL_MINB_F32_W7)
-sweep_roll_f32(SweepArgs<float> A) {
-    sweep_roll_body<float, ORDER, DIR>(A);
+template <class T, int ORDER>
+struct RollMinBlocks {
+    static constexpr int value = sizeof(T) == 4 ? (ORDER == 5 ? RH_ROLL_MINB_F32_W5 : RH_ROLL_MINB_F32_W7)
+                                                : (ORDER == 5 ? RH_ROLL_MINB_F64_W5 : RH_ROLL_MINB_F64_W7);
+};
+
+template <class T, int ORDER, int TX>
+__global__ void __launch_bounds__(256) sweep_x(SweepArgs<T> A) {
+    sweep_x_body<T, ORDER, TX>(A, blockIdx.x);
 }
-template <int ORDER, int DIR>
-__global__ void __launch_bounds__(256, ORDER == 5 ? RH_ROLL_MINB_F64_W5 : RH_ROLL_MINB_F64_W7)
-sweep_roll_f64(SweepArgs<double> A) {
-    sweep_roll_body<double, ORDER, DIR>(A);
+
+template <class T, int ORDER, int DIR>
+__global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_roll(SweepArgs<T> A) {
+    sweep_roll_body<T, ORDER, DIR>(A, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweeps: one launch covers the same sweep of every grid of an event
+// ensemble.  Each grid owns a contiguous range of the launch's blocks; a block
+// finds its grid by binary search over the per-grid first-block table and runs
+// the single-grid body on that grid's slice of the concatenated buffers.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ int find_grid(const BatchArgs<T>& B, int cls, int blk) {
+    int lo = 0, hi = B.ngrid - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.grids[mid].blk0[cls] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class T>
+__device__ __forceinline__ SweepArgs<T> grid_args(const BatchArgs<T>& B, int g, int d) {
+    const BatchGrid<T>& G = B.grids[g];
+    SweepArgs<T> A = B.base;
+    A.us = B.base.us + G.off;
+    A.u0 = B.base.u0 + G.off;
+    A.lacc = B.base.lacc + G.off;
+    A.uout = B.base.uout ? B.base.uout + G.off : nullptr;
+    A.fstride = (long long)G.n[0] * G.n[1] * G.n[2];
+    A.n[0] = G.n[0];
+    A.n[1] = G.n[1];
+    A.n[2] = G.n[2];
+    A.bc = G.bc[d];
+    A.inv_h = G.inv_h[d];
+    A.seg = G.seg[d];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        A.hb.c0[a] = G.c0[a];
+        A.hb.h[a] = G.h[a];
+    }
+    return A;
+}
+
+template <class T, int ORDER, int TX>
+__global__ void __launch_bounds__(256) sweep_x_batch(BatchArgs<T> B) {
+    const int g = find_grid(B, 0, blockIdx.x);
+    const SweepArgs<T> A = grid_args(B, g, 0);
+    sweep_x_body<T, ORDER, TX>(A, blockIdx.x - B.grids[g].blk0[0]);
+}
+
+template <class T, int ORDER, int DIR>
+__global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_roll_batch(BatchArgs<T> B) {
+    const int g = find_grid(B, DIR, blockIdx.x);
+    const SweepArgs<T> A = grid_args(B, g, DIR);
+    const int lb = blockIdx.x - B.grids[g].blk0[DIR];
+    const int gx = B.grids[g].nchunk[DIR];
+    sweep_roll_body<T, ORDER, DIR>(A, (unsigned)(lb % gx), lb / gx);
 }
 
 // Stage combine with L = 0 (grids with no axis longer than one cell).
@@ -517,8 +580,7 @@ static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
     const int seg = choose_segment(a.n[DIR], (int)(gx * 256));
     a.seg = seg;
     const unsigned gy = (a.n[DIR] + seg - 1) / seg;
-    if constexpr (sizeof(T) == 4) sweep_roll_f32<ORDER, DIR><<<dim3(gx, gy), dim3(256), 0, s>>>(a);
-    else sweep_roll_f64<ORDER, DIR><<<dim3(gx, gy), dim3(256), 0, s>>>(a);
+    sweep_roll<T, ORDER, DIR><<<dim3(gx, gy), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -532,6 +594,44 @@ hipError_t launch_sweep(int dir, int order, const SweepArgs<T>& a, hipStream_t s
     if (dir == 0) return launch_x<T, 7>(a, s);
     if (dir == 1) return launch_roll<T, 7, 1>(a, s);
     return launch_roll<T, 7, 2>(a, s);
+}
+
+template <class T>
+hipError_t launch_sweep_batch(int dir, int order, int tx, const BatchArgs<T>& b, int nblocks,
+                              hipStream_t s) {
+    const dim3 grid(nblocks), block(256);
+    if (dir == 0) {
+        if (order == 5) {
+            if (tx == 64) sweep_x_batch<T, 5, 64><<<grid, block, 0, s>>>(b);
+            else if (tx == 32) sweep_x_batch<T, 5, 32><<<grid, block, 0, s>>>(b);
+            else sweep_x_batch<T, 5, 16><<<grid, block, 0, s>>>(b);
+        } else {
+            if (tx == 64) sweep_x_batch<T, 7, 64><<<grid, block, 0, s>>>(b);
+            else if (tx == 32) sweep_x_batch<T, 7, 32><<<grid, block, 0, s>>>(b);
+            else sweep_x_batch<T, 7, 16><<<grid, block, 0, s>>>(b);
+        }
+    } else if (dir == 1) {
+        if (order == 5) sweep_roll_batch<T, 5, 1><<<grid, block, 0, s>>>(b);
+        else sweep_roll_batch<T, 7, 1><<<grid, block, 0, s>>>(b);
+    } else {
+        if (order == 5) sweep_roll_batch<T, 5, 2><<<grid, block, 0, s>>>(b);
+        else sweep_roll_batch<T, 7, 2><<<grid, block, 0, s>>>(b);
+    }
+    return hipGetLastError();
+}
+
+// Blocks of one grid in each sweep class for a batched launch (x tile width tx,
+// rolling segment seg_y / seg_z); fills blk counts and the rolling chunk counts.
+void batch_blocks(const int n[3], int tx, const int seg[3], int blocks[3], int nchunk[3]) {
+    const int ty = 256 / tx;
+    blocks[0] = ((n[0] + tx - 1) / tx) * (int)(((long long)n[1] * n[2] + ty - 1) / ty);
+    nchunk[0] = 0;
+    for (int d = 1; d < 3; ++d) {
+        const int wd = d == 1 ? 2 : 1;
+        const long long cols = (long long)n[0] * n[wd];
+        nchunk[d] = (int)((cols + 255) / 256);
+        blocks[d] = nchunk[d] * ((n[d] + seg[d] - 1) / seg[d]);
+    }
 }
 
 static unsigned elementwise_blocks(long long n) {
@@ -574,7 +674,8 @@ hipError_t launch_totals(const T* state, long long n, double* partials, int nblk
     template hipError_t launch_set_fields<T>(T*, const double*, int, long long, hipStream_t);      \
     template hipError_t launch_get_fields<T>(const T*, double*, int, long long, unsigned*,         \
                                              hipStream_t);                                         \
-    template hipError_t launch_totals<T>(const T*, long long, double*, int, double*, hipStream_t);
+    template hipError_t launch_totals<T>(const T*, long long, double*, int, double*, hipStream_t); \
+    template hipError_t launch_sweep_batch<T>(int, int, int, const BatchArgs<T>&, int, hipStream_t);
 
 RH_INSTANTIATE(float)
 RH_INSTANTIATE(double)

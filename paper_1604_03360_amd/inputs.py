@@ -117,9 +117,14 @@ def hotspots(event, size=None, h=0.15, order=5, nsteps=100, mean_spots=50, sigma
         d = d - box * np.round(d / box)
         return np.exp(-d * d / (2.0 * sigma * sigma))
 
-    for k in range(K):
-        gx, gy, gz = g1(centres[k, 0]), g1(centres[k, 1]), g1(centres[k, 2])
-        e += amps[k] * (gz[:, None, None] * (gy[:, None] * gx[None, :])[None, :, :])
+    if K:
+        # sum of K separable Gaussians as one (n x K) @ (K x n^2) product
+        gx = np.stack([g1(c) for c in centres[:, 0]])
+        gy = np.stack([g1(c) for c in centres[:, 1]])
+        gz = np.stack([g1(c) for c in centres[:, 2]])
+        zk = (gz * amps[:, None]).T                        # (n, K)
+        kyx = (gy[:, :, None] * gx[:, None, :]).reshape(K, n * n)
+        e += (zk @ kyx).reshape(n, n, n)
     prim = np.zeros((5, n, n, n))
     prim[0] = e
     prim[4] = e ** 0.75

@@ -70,6 +70,27 @@ def library():
         L.rh_reset_counters.argtypes = [vp]
         L.rh_set_timing.argtypes = [vp, i]
         L.rh_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), i]
+        llp = ctypes.POINTER(ctypes.c_longlong)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.rh_batch_create.argtypes = [pp, i, ctypes.POINTER(rh_grid_desc)]
+        L.rh_batch_destroy.argtypes = [vp]
+        L.rh_batch_destroy.restype = None
+        L.rh_batch_offsets.argtypes = [vp, llp]
+        L.rh_batch_state_bytes.argtypes = [vp]
+        L.rh_batch_state_bytes.restype = ctypes.c_size_t
+        L.rh_batch_workspace_bytes.argtypes = [vp]
+        L.rh_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.rh_batch_bind.argtypes = [vp, vp, vp, vp]
+        L.rh_batch_set_fields.argtypes = [vp, vp, i]
+        L.rh_batch_get_fields.argtypes = [vp, vp, i]
+        L.rh_batch_step.argtypes = [vp, d, i, dp]
+        L.rh_batch_totals.argtypes = [vp, dp, llp]
+        L.rh_batch_set_graph.argtypes = [vp, i]
+        L.rh_batch_set_tuning.argtypes = [vp, i, i, i]
+        L.rh_batch_get_tuning.argtypes = [vp, ip, ip, ip]
+        L.rh_batch_autotune.argtypes = [vp, i]
+        L.rh_batch_set_timing.argtypes = [vp, i]
+        L.rh_batch_kernel_times.argtypes = [vp, dp, llp, i]
         _lib = L
     return _lib
 
@@ -233,6 +254,156 @@ class Hydro:
             self.torch.cuda.current_stream(self.device).synchronize()
             rh_plan_destroy(self.plan)
             self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Event-by-event batches
+# ---------------------------------------------------------------------------
+def rh_batch_create(descs):
+    arr = (rh_grid_desc * len(descs))(*descs)
+    b = ctypes.c_void_p()
+    _check(library().rh_batch_create(ctypes.byref(b), len(descs), arr))
+    return b
+
+
+def rh_batch_destroy(batch):
+    library().rh_batch_destroy(batch)
+
+
+def rh_batch_offsets(batch, n_grids):
+    out = (ctypes.c_longlong * (n_grids + 1))()
+    _check(library().rh_batch_offsets(batch, out))
+    return list(out)
+
+
+def rh_batch_state_bytes(batch):
+    return library().rh_batch_state_bytes(batch)
+
+
+def rh_batch_workspace_bytes(batch):
+    return library().rh_batch_workspace_bytes(batch)
+
+
+def rh_batch_bind(batch, state_ptr, workspace_ptr, stream_ptr):
+    _check(library().rh_batch_bind(batch, ctypes.c_void_p(state_ptr), ctypes.c_void_p(workspace_ptr),
+                                   ctypes.c_void_p(stream_ptr)))
+
+
+def rh_batch_set_fields(batch, src_ptr, kind):
+    _check(library().rh_batch_set_fields(batch, ctypes.c_void_p(src_ptr), kind))
+
+
+def rh_batch_get_fields(batch, dst_ptr, kind):
+    _check(library().rh_batch_get_fields(batch, ctypes.c_void_p(dst_ptr), kind))
+
+
+def rh_batch_step(batch, dt, n_steps, t):
+    tt = ctypes.c_double(t)
+    _check(library().rh_batch_step(batch, float(dt), int(n_steps), ctypes.byref(tt)))
+    return tt.value
+
+
+def rh_batch_totals(batch, n_grids):
+    out = (ctypes.c_double * (5 * n_grids))()
+    cnt = (ctypes.c_longlong * 2)()
+    _check(library().rh_batch_totals(batch, out, cnt))
+    return [list(out[5 * g:5 * g + 5]) for g in range(n_grids)], list(cnt)
+
+
+def rh_batch_set_graph(batch, enable):
+    _check(library().rh_batch_set_graph(batch, int(bool(enable))))
+
+
+def rh_batch_set_tuning(batch, tile_x, seg_y, seg_z):
+    _check(library().rh_batch_set_tuning(batch, int(tile_x), int(seg_y), int(seg_z)))
+
+
+def rh_batch_get_tuning(batch):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(library().rh_batch_get_tuning(batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def rh_batch_autotune(batch, reps=3):
+    _check(library().rh_batch_autotune(batch, int(reps)))
+    return rh_batch_get_tuning(batch)
+
+
+def rh_batch_set_timing(batch, enable):
+    _check(library().rh_batch_set_timing(batch, int(bool(enable))))
+
+
+def rh_batch_kernel_times(batch):
+    ms = (ctypes.c_double * RH_KERNEL_CLASSES)()
+    cnt = (ctypes.c_longlong * RH_KERNEL_CLASSES)()
+    _check(library().rh_batch_kernel_times(batch, ms, cnt, RH_KERNEL_CLASSES))
+    return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(RH_KERNEL_CLASSES)}
+
+
+class Batch:
+    """An event ensemble on the GPU: one concatenated state and workspace owned
+    by torch; the library advances all grids with batched launches."""
+
+    def __init__(self, specs, precision=RH_PREC_FP32, scheme=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.specs = specs
+        self.descs = [make_desc(sp["shape"], sp["h"], sp["c0"], scheme or sp["order"], precision,
+                                sp["bc"], sp.get("eps", 1e-6), sp.get("hub", (10.0, 1.0, 0.5)))
+                      for sp in specs]
+        self.batch = rh_batch_create(self.descs)
+        self.n = len(specs)
+        self.offsets = rh_batch_offsets(self.batch, self.n)
+        self.dtype = torch.float32 if precision == RH_PREC_FP32 else torch.float64
+        total = self.offsets[-1]
+        self.state = torch.zeros(total, dtype=self.dtype, device=self.device)
+        self.workspace = torch.zeros(3 * total, dtype=self.dtype, device=self.device)
+        self.t = float(specs[0].get("t0", 0.0))
+        rh_batch_bind(self.batch, self.state.data_ptr(), self.workspace.data_ptr(),
+                      torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _concat(self, arrays):
+        import numpy as np
+        buf = np.zeros(self.offsets[-1], dtype=np.float64)
+        for g, a in enumerate(arrays):
+            a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+            buf[self.offsets[g]:self.offsets[g] + a.size] = a
+        return self.torch.from_numpy(buf).to(self.device)
+
+    def set_primitive(self, prims):
+        src = self._concat(prims)
+        rh_batch_set_fields(self.batch, src.data_ptr(), RH_FIELDS_PRIMITIVE)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def get(self, kind=RH_FIELDS_CONSERVED):
+        dst = self.torch.empty(self.offsets[-1], dtype=self.torch.float64, device=self.device)
+        rh_batch_get_fields(self.batch, dst.data_ptr(), kind)
+        host = dst.cpu().numpy()
+        out = []
+        for g, sp in enumerate(self.specs):
+            nx, ny, nz = sp["shape"]
+            out.append(host[self.offsets[g]:self.offsets[g] + 5 * nx * ny * nz].reshape(5, nz, ny, nx))
+        return out
+
+    def step(self, dt, n_steps=1):
+        self.t = rh_batch_step(self.batch, dt, n_steps, self.t)
+        return self.t
+
+    def totals(self):
+        return rh_batch_totals(self.batch, self.n)
+
+    def close(self):
+        if self.batch is not None:
+            self.torch.cuda.current_stream(self.device).synchronize()
+            rh_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

@@ -523,3 +523,71 @@ def test_riemann_star_regression(orc):
     _, s = orc.riemann_conformal(1.0, 1.0, 0.1, 0.125, np.zeros(1))
     for k, v in rec["star"].items():
         assert s[k] == pytest.approx(v, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Adjoint: the hand-written VJP against the complex-step JVP (dot-product test)
+# and against the transpose built column by column on a tiny grid.
+# ---------------------------------------------------------------------------
+def _adjoint_cases():
+    return [
+        ("periodic", inputs.random_smooth((9, 7, 6), h=0.1, seed=21)),
+        ("outflow", inputs.random_smooth((8, 6, 7), h=0.1, seed=22, bc=(OUT,) * 3)),
+        ("hubble", inputs.hubble(n=8, half_width=3.0)),
+        ("hotspots", inputs.hotspots(5, size=10)),
+    ]
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_vjp_L_dot_product(orc, order):
+    for name, spec in _adjoint_cases():
+        g = orc.grid_from_spec(spec, order=order)
+        u = orc.prim2con(spec["prim"])
+        rng = np.random.default_rng(31)
+        v = rng.normal(size=u.shape)
+        w = rng.normal(size=u.shape)
+        t = spec["t0"] + 0.1
+        lhs = np.vdot(w, orc.jvp_L(g, u, v, t=t))
+        rhs = np.vdot(orc.vjp_L(g, u, w, t=t), v)
+        assert rhs == pytest.approx(lhs, rel=1e-11), name
+
+
+def test_vjp_L_full_transpose_tiny(orc):
+    spec = inputs.random_smooth((4, 3, 3), h=0.2, seed=23)
+    for order in (5, 7):
+        g = orc.grid_from_spec(spec, order=order)
+        u = orc.prim2con(spec["prim"])
+        n = u.size
+        J = np.empty((n, n))
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = 1.0
+            J[:, j] = orc.jvp_L(g, u, e.reshape(u.shape)).ravel()
+        w = np.random.default_rng(3).normal(size=u.shape)
+        np.testing.assert_allclose(orc.vjp_L(g, u, w).ravel(), J.T @ w.ravel(), rtol=1e-11,
+                                   atol=1e-11 * np.abs(J.T @ w.ravel()).max())
+
+
+def test_vjp_charge_is_passive(orc):
+    """E and M do not depend on N (p = e/3), so weights on E and M alone give a
+    zero adjoint for N."""
+    spec = inputs.random_smooth((7, 6, 5), h=0.1, seed=24)
+    g = orc.grid_from_spec(spec)
+    u = orc.prim2con(spec["prim"])
+    w = np.random.default_rng(4).normal(size=u.shape)
+    w[4] = 0.0
+    assert np.all(orc.vjp_L(g, u, w)[4] == 0.0)
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_vjp_step_dot_product(orc, order):
+    for name, spec in _adjoint_cases()[:3]:
+        g = orc.grid_from_spec(spec, order=order)
+        u = orc.prim2con(spec["prim"])
+        rng = np.random.default_rng(41)
+        v = rng.normal(size=u.shape)
+        w = rng.normal(size=u.shape)
+        dt, t = spec["dt"], spec["t0"]
+        lhs = np.vdot(w, orc.jvp_step(g, u, v, dt, t=t))
+        rhs = np.vdot(orc.vjp_step(g, u, w, dt, t=t), v)
+        assert rhs == pytest.approx(lhs, rel=1e-11), name
