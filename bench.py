@@ -103,6 +103,44 @@ def run_gpu(spec, precision, steps, warmup):
             "kernels": ktimes, "totals": tot, "counters": cnt}
 
 
+def run_adjoint(spec, precision, reps):
+    """Time the adjoint of one SSP-RK3 step (stage recomputation included) and one
+    forward step on the same plan, both with the state resident in HBM."""
+    import torch
+    from paper_1604_03360_amd import rh
+    prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    h.set_primitive(spec["prim"])
+    dt = spec["dt"]
+    h.step(dt, 1)
+    u_n = h.state.clone()
+    ubar = torch.randn_like(u_n)
+    out = h.step_vjp(u_n, ubar, dt)            # warm-up, allocates scratch
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    rh.rh_set_timing(h.plan, 1)
+    e[0].record(stream)
+    for _ in range(reps):
+        out = h.step_vjp(u_n, ubar, dt)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    kt = rh.rh_kernel_times(h.plan)
+    rh.rh_set_timing(h.plan, 0)
+    e[2].record(stream)
+    h.step(dt, reps)
+    e[3].record(stream)
+    torch.cuda.synchronize()
+    adj_ms = e[0].elapsed_time(e[1]) / reps
+    fwd_ms = e[2].elapsed_time(e[3]) / reps
+    finite = bool(torch.isfinite(out).all().item())
+    h.close()
+    del h, u_n, ubar, out
+    torch.cuda.empty_cache()
+    return {"step_vjp_ms": adj_ms, "step_ms": fwd_ms, "ratio": adj_ms / fwd_ms, "finite": finite,
+            "adjoint_sweeps_ms_per_step_vjp": kt["adjoint"][0] / reps}
+
+
 def roofline(run, precision, order, ncell):
     elem = 4 if precision == "fp32" else 8
     kern = {k: v for k, v in run["kernels"].items() if k.startswith("sweep")}
@@ -151,6 +189,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (reference "
                          "for scaling hardware byte counters)")
@@ -183,6 +222,11 @@ def main():
         r64 = run_gpu(spec, "fp64", args.steps, args.warmup)
         print("bench: fp64 %.4g cell-updates/s (%.3f ms/step)" % (r64["value"], r64["ms_per_step"]),
               file=sys.stderr, flush=True)
+    adj = None
+    if not args.no_adjoint:
+        adj = run_adjoint(spec, "fp32", 3)
+        print("bench: adjoint step %.3f ms vs forward step %.3f ms (ratio %.2f)"
+              % (adj["step_vjp_ms"], adj["step_ms"], adj["ratio"]), file=sys.stderr, flush=True)
     dom, roof, hbm = roofline(r32, "fp32", args.scheme, ncell)
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "cell-updates/s", "n_gpus": 1,
@@ -198,6 +242,9 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in r32["kernels"].items()},
         "counters": r32["counters"],
     }
+    if adj is not None:
+        out["adjoint"] = dict(adj, workload="same grid, FP32, adjoint of one SSP-RK3 step "
+                                           "(stage recomputation included) / one forward step")
     if r64 is not None:
         _, roof64, hbm64 = roofline(r64, "fp64", args.scheme, ncell)
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],

@@ -66,7 +66,8 @@ typedef int rh_status;
 #define RH_KERNEL_SWEEP_Y 1   /* y-direction WENO sweep */
 #define RH_KERNEL_SWEEP_Z 2   /* z-direction WENO sweep */
 #define RH_KERNEL_OTHER   3   /* combine, conversion and reduction kernels */
-#define RH_KERNEL_CLASSES 4
+#define RH_KERNEL_ADJOINT 4   /* adjoint sweeps (all axes) */
+#define RH_KERNEL_CLASSES 5
 
 typedef struct rh_grid_desc {
     int nx, ny, nz;          /* cells per axis, each >= 1 */
@@ -162,6 +163,34 @@ rh_status rh_set_timing(rh_plan* plan, int enable);
  * recorded since timing was enabled.  ms_out and launches_out hold n entries
  * (n <= RH_KERNEL_CLASSES).  Synchronises the stream. */
 rh_status rh_kernel_times(rh_plan* plan, double* ms_out, long long* launches_out, int n);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative) of L and of one SSP-RK3 step.  The paper
+ * integrates du/dt = L(u) (Sec. 1, Eq. (2)); these calls give the transposed
+ * Jacobians needed to differentiate a run with respect to its initial state.
+ * The derivative is that of the discrete scheme actually computed, including
+ * the WENO nonlinear weights (Sec. 1.2) and the primitive-recovery floors.
+ * ------------------------------------------------------------------------ */
+
+/* out = J(u)^T w, J = dL/du of Eq. (2) at state u and time t.  u, w and out are
+ * device buffers of the plan precision and layout [5][nz][ny][nx]; out must
+ * not alias u or w.  The plan need not be bound; work goes to the bound stream
+ * (or the default stream if unbound).  Errors: RH_E_INVAL (NULL or aliasing). */
+rh_status rh_apply_vjp(rh_plan* plan, double t, const void* u, const void* w, void* out);
+
+/* Bytes of the scratch buffer rh_step_vjp needs (four states). */
+size_t rh_vjp_workspace_bytes(const rh_plan* plan);
+
+/* Adjoint of one SSP-RK3 step taken from u_n at time t with step dt:
+ * ubar_out = (d u_{n+1} / d u_n)^T ubar_in.  The stage states u1, u2 are
+ * recomputed into scratch (rh_vjp_workspace_bytes), then
+ *   b2 = 2/3 b + 2/3 dt J(u2)^T b,  b1 = 1/4 b2 + 1/4 dt J(u1)^T b2,
+ *   ubar_out = 1/3 b + 3/4 b2 + b1 + dt J(u_n)^T b1   (b = ubar_in),
+ * with J(u2) at t + dt/2, J(u1) at t + dt, J(u_n) at t.  The plan must be bound
+ * (its workspace holds the L accumulator of the recomputation).  ubar_out may
+ * alias ubar_in.  Errors: RH_E_STATE (unbound), RH_E_INVAL. */
+rh_status rh_step_vjp(rh_plan* plan, double t, double dt, const void* u_n, const void* ubar_in,
+                      void* ubar_out, void* scratch);
 
 /* ------------------------------------------------------------------------
  * Event-by-event ensembles (batched grids).  The paper's motivation is

@@ -1,0 +1,224 @@
+// rh_adjoint.hpp -- device arithmetic of the hand-written adjoint of L.
+//
+// With w a field of weights, sum_i w_i . L_i (Eq. (2) of Sikorski et al.,
+// arXiv:1604.03360) equals the sum over faces of Fhat(i+1/2) . g(i+1/2) with
+// g = (w_{i+1} - w_i) / h; its gradient with respect to the state is therefore
+// built face by face: the gradient of each WENO reconstruction (Sec. 1.2) with
+// respect to its stencil, scaled by g, is accumulated on the stencil cells, and
+// each cell's accumulated split-flux adjoints a+- are mapped through the split
+// f+- = (F(u) +- u)/2 and the flux Jacobian of F (primitive recovery included).
+#pragma once
+#include "rh_device.hpp"
+
+namespace rh {
+
+// Gradient of weno5 (difference form, see weno5) times gbar, added to out[0..4].
+// With omega_k the nonlinear weights, dq_k the candidates minus the centre and
+// G_k = 13/3 A_k^2 + B_k^2 + 4 eps:
+//   d fhat / d s = e_2 + sum_k omega_k grad(dq_k)
+//                  - 2 sum_k omega_k (dq_k - fhat + s2) / G_k grad(G_k),
+//   grad(G_k) = 26/3 A_k grad(A_k) + 2 B_k grad(B_k).
+template <class T>
+__device__ __forceinline__ void weno5_grad_acc(T s0, T s1, T s2, T s3, T s4, T eps4, T gbar,
+                                               T& o0, T& o1, T& o2, T& o3, T& o4) {
+    const T E1 = s1 - s0, E2 = s2 - s1, E3 = s3 - s2, E4 = s4 - s3;
+    const T dq0 = (T)(5.0 / 6.0) * E2 - (T)(1.0 / 3.0) * E1;
+    const T dq1 = (T)(1.0 / 6.0) * E2 + (T)(1.0 / 3.0) * E3;
+    const T dq2 = (T)(2.0 / 3.0) * E3 - (T)(1.0 / 6.0) * E4;
+    const T A0 = E2 - E1, A1 = E3 - E2, A2 = E4 - E3;
+    const T B0 = (T)3 * E2 - E1, B1 = E2 + E3, B2 = E4 - (T)3 * E3;
+    const T c133 = (T)(13.0 / 3.0);
+    const T G0 = (c133 * A0) * A0 + (B0 * B0 + eps4);
+    const T G1 = (c133 * A1) * A1 + (B1 * B1 + eps4);
+    const T G2 = (c133 * A2) * A2 + (B2 * B2 + eps4);
+    const T g0 = G0 * G0, g1 = G1 * G1, g2 = G2 * G2;
+    const T w0 = (T)0.1 * (g1 * g2), w1 = (T)0.6 * (g0 * g2), w2 = (T)0.3 * (g0 * g1);
+    const T rs = fast_rcp(w0 + w1 + w2);
+    const T om0 = w0 * rs, om1 = w1 * rs, om2 = w2 * rs;
+    const T fd = om0 * dq0 + om1 * dq1 + om2 * dq2;
+    const T c0 = (T)(-2.0) * om0 * (dq0 - fd) * fast_rcp(G0);
+    const T c1 = (T)(-2.0) * om1 * (dq1 - fd) * fast_rcp(G1);
+    const T c2 = (T)(-2.0) * om2 * (dq2 - fd) * fast_rcp(G2);
+    const T pA0 = (T)(26.0 / 3.0) * c0 * A0, pA1 = (T)(26.0 / 3.0) * c1 * A1, pA2 = (T)(26.0 / 3.0) * c2 * A2;
+    const T pB0 = (T)2 * c0 * B0, pB1 = (T)2 * c1 * B1, pB2 = (T)2 * c2 * B2;
+    // grad(dq): (1/3, -7/6, 5/6, 0, 0), (0, -1/6, -1/6, 1/3, 0), (0, 0, -2/3, 5/6, -1/6)
+    // grad(A):  (1, -2, 1, 0, 0), (0, 1, -2, 1, 0), (0, 0, 1, -2, 1)
+    // grad(B):  (1, -4, 3, 0, 0), (0, -1, 0, 1, 0), (0, 0, 3, -4, 1)
+    const T d0 = (T)(1.0 / 3.0) * om0 + pA0 + pB0;
+    const T d1 = (T)(-7.0 / 6.0) * om0 - (T)(1.0 / 6.0) * om1 - (T)2 * pA0 + pA1 - (T)4 * pB0 - pB1;
+    const T d2 = (T)1 + (T)(5.0 / 6.0) * om0 - (T)(1.0 / 6.0) * om1 - (T)(2.0 / 3.0) * om2 + pA0
+               - (T)2 * pA1 + pA2 + (T)3 * pB0 + (T)3 * pB2;
+    const T d3 = (T)(1.0 / 3.0) * om1 + (T)(5.0 / 6.0) * om2 + pA1 - (T)2 * pA2 + pB1 - (T)4 * pB2;
+    const T d4 = (T)(-1.0 / 6.0) * om2 + pA2 + pB2;
+    o0 += gbar * d0;
+    o1 += gbar * d1;
+    o2 += gbar * d2;
+    o3 += gbar * d3;
+    o4 += gbar * d4;
+}
+
+// Gradient of weno7 (see weno7) times gbar, added to o[0..6].  With
+// G_k = a1 (a1 + kk a3h) + a2h^2 + a3h^2 + eps (a2h = r2 a2, a3h = r3 a3,
+// kk = 1/(2 r3)):
+//   grad(G_k) = (2 a1 + kk a3h) grad(a1) + 2 r2 a2h grad(a2) + (a1/2 + 2 r3 a3h) grad(a3).
+template <class T>
+__device__ __forceinline__ void weno7_grad_acc(const T s[7], T eps, T gbar, T o[7]) {
+    const T D1 = s[1] - s[0], D2 = s[2] - s[1], D3 = s[3] - s[2], D4 = s[4] - s[3];
+    const T D5 = s[5] - s[4], D6 = s[6] - s[5];
+    T dq[4], a1[4], a2h[4], a3h[4];
+    dq[0] = (T)0.25 * D1 - (T)(5.0 / 6.0) * D2 + (T)(13.0 / 12.0) * D3;
+    dq[1] = (T)(1.0 / 3.0) * D3 - (T)(1.0 / 12.0) * D2 + (T)0.25 * D4;
+    dq[2] = (T)(1.0 / 12.0) * (D3 - D5) + (T)0.5 * D4;
+    dq[3] = (T)0.75 * D4 - (T)(1.0 / 3.0) * D5 + (T)(1.0 / 12.0) * D6;
+    const T r2 = (T)2.0816659994661326, r3 = (T)6.253998720818545, kk = (T)(0.5 / 6.253998720818545);
+    a1[0] = (T)(7.0 / 24.0) * D1 - (T)(13.0 / 12.0) * D2 + (T)(43.0 / 24.0) * D3;
+    a1[1] = (T)(11.0 / 12.0) * D3 - (T)(5.0 / 24.0) * D2 + (T)(7.0 / 24.0) * D4;
+    a1[2] = (T)(7.0 / 24.0) * D3 + (T)(11.0 / 12.0) * D4 - (T)(5.0 / 24.0) * D5;
+    a1[3] = (T)(43.0 / 24.0) * D4 - (T)(13.0 / 12.0) * D5 + (T)(7.0 / 24.0) * D6;
+    a2h[0] = r2 * ((T)0.5 * D1 - (T)1.5 * D2 + D3);
+    a2h[1] = r2 * ((T)0.5 * (D4 - D3));
+    a2h[2] = a2h[1];
+    a2h[3] = r2 * ((T)1.5 * D5 - D4 - (T)0.5 * D6);
+    a3h[0] = (r3 / (T)6) * ((D1 + D3) - (T)2 * D2);
+    a3h[1] = (r3 / (T)6) * ((D2 + D4) - (T)2 * D3);
+    a3h[2] = (r3 / (T)6) * ((D3 + D5) - (T)2 * D4);
+    a3h[3] = (r3 / (T)6) * ((D4 + D6) - (T)2 * D5);
+    T G[4], al[4];
+    T sum = (T)0;
+    const T dk[4] = {(T)(1.0 / 35.0), (T)(12.0 / 35.0), (T)(18.0 / 35.0), (T)(4.0 / 35.0)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        G[k] = a1[k] * (a1[k] + kk * a3h[k]) + (a2h[k] * a2h[k] + (a3h[k] * a3h[k] + eps));
+        const T rg = fast_rcp(G[k]);
+        al[k] = dk[k] * rg * rg;
+        sum += al[k];
+    }
+    const T rs = fast_rcp(sum);
+    T om[4], fd = (T)0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        om[k] = al[k] * rs;
+        fd += om[k] * dq[k];
+    }
+    // gradient tables in s0..s6 (a2, a3 unscaled)
+    const T gdq[4][7] = {{(T)(-0.25), (T)(13.0 / 12), (T)(-23.0 / 12), (T)(13.0 / 12), 0, 0, 0},
+                         {0, (T)(1.0 / 12), (T)(-5.0 / 12), (T)(1.0 / 12), (T)0.25, 0, 0},
+                         {0, 0, (T)(-1.0 / 12), (T)(-5.0 / 12), (T)(7.0 / 12), (T)(-1.0 / 12), 0},
+                         {0, 0, 0, (T)(-0.75), (T)(13.0 / 12), (T)(-5.0 / 12), (T)(1.0 / 12)}};
+    const T ga1[4][7] = {{(T)(-7.0 / 24), (T)(11.0 / 8), (T)(-23.0 / 8), (T)(43.0 / 24), 0, 0, 0},
+                         {0, (T)(5.0 / 24), (T)(-9.0 / 8), (T)(5.0 / 8), (T)(7.0 / 24), 0, 0},
+                         {0, 0, (T)(-7.0 / 24), (T)(-5.0 / 8), (T)(9.0 / 8), (T)(-5.0 / 24), 0},
+                         {0, 0, 0, (T)(-43.0 / 24), (T)(23.0 / 8), (T)(-11.0 / 8), (T)(7.0 / 24)}};
+    const T ga2[4][7] = {{(T)(-0.5), (T)2, (T)(-2.5), (T)1, 0, 0, 0},
+                         {0, 0, (T)0.5, (T)(-1), (T)0.5, 0, 0},
+                         {0, 0, (T)0.5, (T)(-1), (T)0.5, 0, 0},
+                         {0, 0, 0, (T)1, (T)(-2.5), (T)2, (T)(-0.5)}};
+    const T ga3[4][7] = {{(T)(-1.0 / 6), (T)0.5, (T)(-0.5), (T)(1.0 / 6), 0, 0, 0},
+                         {0, (T)(-1.0 / 6), (T)0.5, (T)(-0.5), (T)(1.0 / 6), 0, 0},
+                         {0, 0, (T)(-1.0 / 6), (T)0.5, (T)(-0.5), (T)(1.0 / 6), 0},
+                         {0, 0, 0, (T)(-1.0 / 6), (T)0.5, (T)(-0.5), (T)(1.0 / 6)}};
+    T d[7] = {0, 0, 0, (T)1, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T c = (T)(-2.0) * om[k] * (dq[k] - fd) * fast_rcp(G[k]);
+        const T p1 = c * ((T)2 * a1[k] + kk * a3h[k]);
+        const T p2 = c * ((T)2 * r2 * a2h[k]);
+        const T p3 = c * ((T)0.5 * a1[k] + (T)2 * r3 * a3h[k]);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) d[j] += om[k] * gdq[k][j] + p1 * ga1[k][j] + p2 * ga2[k][j] + p3 * ga3[k][j];
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) o[j] += gbar * d[j];
+}
+
+// Velocity along DIR and pressure of the closed-form recovery with their
+// gradients with respect to (E, Mx, My, Mz) (N does not enter), including the
+// two floors: below the energy floor v = 0, p = max(E, 0)/3; above the momentum
+// cap M is replaced by sqrt(1 - kVDelta) E M/|M| before the closed form.
+template <int DIR>
+__device__ __forceinline__ void recover_vp_grad(double E, double Mx, double My, double Mz, double& vd,
+                                                double& p, double gv[4], double gp[4]) {
+    for (int q = 0; q < 4; ++q) gv[q] = gp[q] = 0.0;
+    if (E < kEFloor) {
+        vd = 0.0;
+        p = (E > 0.0 ? E : 0.0) / 3.0;
+        gp[0] = E > 0.0 ? 1.0 / 3.0 : 0.0;
+        return;
+    }
+    double M[3] = {Mx, My, Mz};
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    const double cap = (1.0 - kVDelta) * E * E;
+    const bool capped = M2 > cap;
+    double Me[3] = {M[0], M[1], M[2]};
+    double absM = 0.0, absM3 = 0.0;
+    if (capped) {
+        absM = sqrt(M2);
+        absM3 = absM * M2;
+        const double s = sqrt(cap / M2);
+        for (int i = 0; i < 3; ++i) Me[i] = M[i] * s;
+        M2 = cap;
+    }
+    const double D = sqrt(4.0 * E * E - 3.0 * M2);
+    const double a = 2.0 * E + D, b = E + D;
+    const double k = 3.0 / a;
+    vd = k * Me[DIR];
+    p = (E * E - M2) / b;
+    // gradients with respect to (E, Me)
+    const double dk_dE = -(k / a) * (2.0 + 4.0 * E / D);
+    double gve[4], gpe[4];
+    gve[0] = Me[DIR] * dk_dE;
+    gpe[0] = (2.0 * E - p * (1.0 + 4.0 * E / D)) / b;
+    for (int i = 0; i < 3; ++i) {
+        const double dk_dM = 3.0 * k * Me[i] / (a * D);
+        gve[1 + i] = (i == DIR ? k : 0.0) + Me[DIR] * dk_dM;
+        gpe[1 + i] = Me[i] * (3.0 * p / D - 2.0) / b;
+    }
+    if (!capped) {
+        for (int q = 0; q < 4; ++q) {
+            gv[q] = gve[q];
+            gp[q] = gpe[q];
+        }
+        return;
+    }
+    // chain through Me_i = c E M_i / |M|, c = sqrt(1 - kVDelta)
+    const double c = sqrt(1.0 - kVDelta);
+    gv[0] = gve[0];
+    gp[0] = gpe[0];
+    for (int i = 0; i < 3; ++i) {
+        gv[0] += gve[1 + i] * c * M[i] / absM;
+        gp[0] += gpe[1 + i] * c * M[i] / absM;
+    }
+    for (int j = 0; j < 3; ++j) {
+        double sv = 0.0, sp = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            const double dMe = c * E * ((i == j ? 1.0 : 0.0) / absM - M[i] * M[j] / absM3);
+            sv += gve[1 + i] * dMe;
+            sp += gpe[1 + i] * dMe;
+        }
+        gv[1 + j] = sv;
+        gp[1 + j] = sp;
+    }
+}
+
+// ub += (d f+ / du)^T ap + (d f- / du)^T am for one cell, f+- = (F_DIR(u) +- u)/2.
+template <class T, int DIR>
+__device__ __forceinline__ void split_flux_vjp(const T u[5], const T ap[5], const T am[5], T ub[5]) {
+    double vd, p, gv[4], gp[4];
+    recover_vp_grad<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, p, gv, gp);
+    double lam[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) lam[c] = 0.5 * ((double)ap[c] + (double)am[c]);
+    // F = (M_d, Mx v + p dx, My v + p dy, Mz v + p dz, N v)
+    const double S = lam[1] * (double)u[1] + lam[2] * (double)u[2] + lam[3] * (double)u[3] +
+                     lam[4] * (double)u[4];
+    double g[5];
+    g[0] = S * gv[0] + lam[1 + DIR] * gp[0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[1 + i] = lam[1 + i] * vd + S * gv[1 + i] + lam[1 + DIR] * gp[1 + i];
+    g[1 + DIR] += lam[0];
+    g[4] = lam[4] * vd;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ub[c] += (T)(g[c] + 0.5 * ((double)ap[c] - (double)am[c]));
+}
+
+}  // namespace rh

@@ -923,3 +923,124 @@ rh_status rh_batch_kernel_times(rh_batch* b, double* ms_out, long long* launches
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Adjoint of L and of one SSP-RK3 step
+// ===========================================================================
+namespace {
+
+template <class T>
+rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out) {
+    const long long N = 5 * p->ncell;
+    rh_status st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(out, N, p->stream); },
+                                "fill launch");
+    if (st != RH_OK) return st;
+    const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
+    const double h[3] = {p->d.dx, p->d.dy, p->d.dz};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 2) continue;   // a one-cell axis contributes nothing to L
+        rh::AdjArgs<T> a;
+        std::memset(&a, 0, sizeof(a));
+        a.u = u;
+        a.w = w;
+        a.ub = out;
+        a.fstride = p->ncell;
+        a.n[0] = n[0];
+        a.n[1] = n[1];
+        a.n[2] = n[2];
+        a.bc = p->d.bc[d];
+        a.inv_h = (T)(1.0 / h[d]);
+        a.eps = (T)(p->d.weno_eps > 0.0 ? p->d.weno_eps : 1e-6);
+        a.hb.t = t;
+        a.hb.t0 = p->d.hubble_t0;
+        a.hb.e0 = p->d.hubble_e0;
+        a.hb.n0 = p->d.hubble_n0;
+        a.hb.c0[0] = p->d.x0;
+        a.hb.c0[1] = p->d.y0;
+        a.hb.c0[2] = p->d.z0;
+        a.hb.h[0] = h[0];
+        a.hb.h[1] = h[1];
+        a.hb.h[2] = h[2];
+        st = timed_launch(p, RH_KERNEL_ADJOINT,
+                          [&] { return rh::launch_adjoint_sweep<T>(d, p->d.scheme, a, p->stream); },
+                          "adjoint sweep launch");
+        if (st != RH_OK) return st;
+    }
+    return RH_OK;
+}
+
+template <class T>
+rh_status step_vjp_impl(rh_plan* p, double t, double dt, const T* un, const T* bin, T* bout, T* scratch) {
+    const size_t S = 5 * (size_t)p->ncell;
+    T* u1 = scratch;
+    T* u2 = scratch + S;
+    T* b2 = scratch + 2 * S;
+    T* tmp = scratch + 3 * S;
+    T* Lc = (T*)p->ws + 2 * S;   // the bound workspace's L accumulator
+    rh_status st = evaluate<T>(p, un, un, Lc, u1, t, dt, rh::STAGE_1);
+    if (st == RH_OK) st = evaluate<T>(p, u1, un, Lc, u2, t + dt, dt, rh::STAGE_2);
+    if (st != RH_OK) return st;
+    const long long N = (long long)S;
+    const T td = (T)dt;
+    auto lin = [&](T* out, T a, const T* X, T b, const T* Y, T c, const T* Z, T d, const T* V) {
+        return timed_launch(p, RH_KERNEL_OTHER,
+                            [&] { return rh::launch_lincomb<T>(out, N, a, X, b, Y, c, Z, d, V, p->stream); },
+                            "combine launch");
+    };
+    // b2 = 2/3 b + 2/3 dt J(u2)^T b
+    if ((st = vjp_impl<T>(p, t + 0.5 * dt, u2, bin, tmp)) != RH_OK) return st;
+    if ((st = lin(b2, (T)(2.0 / 3.0), bin, (T)(2.0 / 3.0) * td, tmp, (T)0, nullptr, (T)0, nullptr)) != RH_OK)
+        return st;
+    // b1 = 1/4 b2 + 1/4 dt J(u1)^T b2   (b1 stored in u2's slot, u2 no longer needed)
+    T* b1 = u2;
+    if ((st = vjp_impl<T>(p, t + dt, u1, b2, tmp)) != RH_OK) return st;
+    if ((st = lin(b1, (T)0.25, b2, (T)0.25 * td, tmp, (T)0, nullptr, (T)0, nullptr)) != RH_OK) return st;
+    // out = 1/3 b + 3/4 b2 + b1 + dt J(un)^T b1
+    if ((st = vjp_impl<T>(p, t, un, b1, tmp)) != RH_OK) return st;
+    return lin(bout, (T)(1.0 / 3.0), bin, (T)0.75, b2, (T)1, b1, td, tmp);
+}
+
+// [a, a + na) and [b, b + nb) intersect
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void* out) {
+    if (!p) return fail(RH_E_INVAL, "plan is NULL");
+    if (!u || !w || !out) return fail(RH_E_INVAL, "NULL buffer");
+    const size_t sb = rh_state_bytes(p);
+    if (overlaps(out, sb, u, sb) || overlaps(out, sb, w, sb)) return fail(RH_E_INVAL, "out aliases u or w");
+    return is_fp32(p) ? vjp_impl<float>(p, t, (const float*)u, (const float*)w, (float*)out)
+                      : vjp_impl<double>(p, t, (const double*)u, (const double*)w, (double*)out);
+}
+
+size_t rh_vjp_workspace_bytes(const rh_plan* p) { return p ? 4 * rh_state_bytes(p) : 0; }
+
+rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const void* ubar_in,
+                      void* ubar_out, void* scratch) {
+    rh_status st = check_bound(p);
+    if (st != RH_OK) return st;
+    if (!u_n || !ubar_in || !ubar_out || !scratch) return fail(RH_E_INVAL, "NULL buffer");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
+    const size_t sb = rh_state_bytes(p);
+    if (overlaps(scratch, 4 * sb, u_n, sb) || overlaps(scratch, 4 * sb, ubar_in, sb) ||
+        overlaps(scratch, 4 * sb, ubar_out, sb))
+        return fail(RH_E_INVAL, "scratch aliases an operand");
+    if (overlaps(ubar_out, sb, u_n, sb)) return fail(RH_E_INVAL, "ubar_out aliases u_n");
+    const char* ws = (const char*)p->ws;
+    if (overlaps(ws + 2 * sb, sb, u_n, sb) || overlaps(ws + 2 * sb, sb, ubar_in, sb) ||
+        overlaps(ws + 2 * sb, sb, ubar_out, sb) || overlaps(ws + 2 * sb, sb, scratch, 4 * sb))
+        return fail(RH_E_INVAL, "an operand aliases the bound workspace's L accumulator");
+    return is_fp32(p) ? step_vjp_impl<float>(p, t, dt, (const float*)u_n, (const float*)ubar_in,
+                                             (float*)ubar_out, (float*)scratch)
+                      : step_vjp_impl<double>(p, t, dt, (const double*)u_n, (const double*)ubar_in,
+                                              (double*)ubar_out, (double*)scratch);
+}
+
+}  // extern "C"

@@ -53,6 +53,29 @@ struct BatchArgs {
     int ngrid;
 };
 
+// Adjoint sweep along one axis: ub += (dL_axis/du)(u)^T w.
+template <class T>
+struct AdjArgs {
+    const T* u;         // state at which the Jacobian is taken
+    const T* w;         // weights (adjoint of L)
+    T* ub;              // accumulated adjoint of u (read-modify-write)
+    long long fstride;
+    int n[3];
+    int bc;             // boundary condition of the sweep axis
+    int seg;            // owned segment length along the axis
+    T inv_h;
+    T eps;
+    HubbleBC hb;
+};
+
+template <class T>
+hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s);
+template <class T>
+hipError_t launch_fill_zero(T* p, long long n, hipStream_t s);
+template <class T>
+hipError_t launch_lincomb(T* out, long long n, T a, const T* X, T b, const T* Y, T c, const T* Z, T d,
+                          const T* V, hipStream_t s);
+
 // Launchers (return hipGetLastError() of the launch).
 template <class T>
 hipError_t launch_sweep(int dir, int order, const SweepArgs<T>& a, hipStream_t s);

@@ -18,9 +18,9 @@ RH_OK, RH_E_INVAL, RH_E_NOMEM, RH_E_HIP, RH_E_STATE, RH_E_NOTSUP, RH_E_PHYS = 0,
 RH_PREC_FP64, RH_PREC_FP32 = 0, 1
 RH_BC_PERIODIC, RH_BC_OUTFLOW, RH_BC_HUBBLE = 0, 1, 2
 RH_FIELDS_CONSERVED, RH_FIELDS_PRIMITIVE = 0, 1
-RH_KERNEL_SWEEP_X, RH_KERNEL_SWEEP_Y, RH_KERNEL_SWEEP_Z, RH_KERNEL_OTHER = 0, 1, 2, 3
-RH_KERNEL_CLASSES = 4
-KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other")
+RH_KERNEL_SWEEP_X, RH_KERNEL_SWEEP_Y, RH_KERNEL_SWEEP_Z, RH_KERNEL_OTHER, RH_KERNEL_ADJOINT = 0, 1, 2, 3, 4
+RH_KERNEL_CLASSES = 5
+KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint")
 
 
 class rh_grid_desc(ctypes.Structure):
@@ -70,6 +70,10 @@ def library():
         L.rh_reset_counters.argtypes = [vp]
         L.rh_set_timing.argtypes = [vp, i]
         L.rh_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), i]
+        L.rh_apply_vjp.argtypes = [vp, d, vp, vp, vp]
+        L.rh_vjp_workspace_bytes.argtypes = [vp]
+        L.rh_vjp_workspace_bytes.restype = ctypes.c_size_t
+        L.rh_step_vjp.argtypes = [vp, d, d, vp, vp, vp, vp]
         llp = ctypes.POINTER(ctypes.c_longlong)
         ip = ctypes.POINTER(ctypes.c_int)
         L.rh_batch_create.argtypes = [pp, i, ctypes.POINTER(rh_grid_desc)]
@@ -172,6 +176,21 @@ def rh_kernel_times(plan):
     return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(RH_KERNEL_CLASSES)}
 
 
+def rh_apply_vjp(plan, t, u_ptr, w_ptr, out_ptr):
+    _check(library().rh_apply_vjp(plan, float(t), ctypes.c_void_p(u_ptr), ctypes.c_void_p(w_ptr),
+                                  ctypes.c_void_p(out_ptr)))
+
+
+def rh_vjp_workspace_bytes(plan):
+    return library().rh_vjp_workspace_bytes(plan)
+
+
+def rh_step_vjp(plan, t, dt, un_ptr, bin_ptr, bout_ptr, scratch_ptr):
+    _check(library().rh_step_vjp(plan, float(t), float(dt), ctypes.c_void_p(un_ptr),
+                                 ctypes.c_void_p(bin_ptr), ctypes.c_void_p(bout_ptr),
+                                 ctypes.c_void_p(scratch_ptr)))
+
+
 def make_desc(shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC,) * 3,
               eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False):
     d = rh_grid_desc()
@@ -248,6 +267,28 @@ class Hydro:
 
     def totals(self):
         return rh_totals(self.plan)
+
+    def _dev(self, a):
+        t = self.torch.as_tensor(a)
+        return t.to(device=self.device, dtype=self.dtype).contiguous()
+
+    def vjp(self, u, w, t=None):
+        """J(u)^T w of L (device tensors or arrays of the plan layout)."""
+        u, w = self._dev(u), self._dev(w)
+        out = self.torch.empty_like(u)
+        rh_apply_vjp(self.plan, self.t if t is None else t, u.data_ptr(), w.data_ptr(), out.data_ptr())
+        return out
+
+    def step_vjp(self, u_n, ubar, dt, t=None):
+        """Adjoint of one SSP-RK3 step taken from u_n."""
+        u_n, ubar = self._dev(u_n), self._dev(ubar)
+        out = self.torch.empty_like(u_n)
+        if getattr(self, "_vjp_scratch", None) is None:
+            self._vjp_scratch = self.torch.empty((4,) + tuple(u_n.shape), dtype=self.dtype,
+                                                 device=self.device)
+        rh_step_vjp(self.plan, self.t if t is None else t, dt, u_n.data_ptr(), ubar.data_ptr(),
+                    out.data_ptr(), self._vjp_scratch.data_ptr())
+        return out
 
     def close(self):
         if self.plan is not None:

@@ -1,0 +1,106 @@
+"""Hand-written adjoint on the GPU against the oracle's adjoint and against the
+oracle's complex-step directional derivatives (dot-product test)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_03360_amd import inputs
+from gpu_helpers import rh_module
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "smooth_periodic": lambda o: inputs.random_smooth((37, 29, 23), h=0.1, seed=61, order=o),
+    "smooth_outflow": lambda o: inputs.random_smooth((26, 33, 19), h=0.08, seed=62, order=o,
+                                                     bc=(inputs.BC_OUTFLOW,) * 3),
+    "hubble": lambda o: inputs.hubble(n=20, order=o, half_width=3.0),
+    "hotspots": lambda o: inputs.hotspots(9, size=32, order=o),
+    "tiny_periodic": lambda o: inputs.random_smooth((6, 5, 4), h=0.2, seed=63, order=o),
+}
+
+
+def vjp_errors(got, ref, w, h):
+    """Per-field max|got - ref| normalised by max(max|ref|, max|w|/h): the adjoint
+    is a sum of face weights (w_{i+1} - w_i)/h times O(1) derivatives."""
+    got = np.asarray(got, np.float64).reshape(5, -1)
+    ref = np.asarray(ref, np.float64).reshape(5, -1)
+    scale = max(np.abs(ref).max(), np.abs(w).max() / h)
+    return np.abs(got - ref).max(axis=1) / scale
+
+
+def _setup(rh, spec, prec):
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    u = oracle.prim2con(spec["prim"])
+    w = np.random.default_rng(7).normal(size=u.shape)
+    return h, u, w
+
+
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_vjp_L_fp64_matches_oracle(case, order):
+    rh = rh_module()
+    spec = CASES[case](order)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP64)
+    t = spec["t0"] + 0.2
+    got = h.vjp(u, w, t=t).cpu().numpy()
+    h.close()
+    ref = oracle.vjp_L(oracle.grid_from_spec(spec), u, w, t=t)
+    err = vjp_errors(got, ref, w, min(spec["h"]))
+    print(case, order, err, flush=True)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_vjp_L_dot_product_with_oracle_jvp(order):
+    rh = rh_module()
+    spec = CASES["smooth_periodic"](order)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP64)
+    v = np.random.default_rng(8).normal(size=u.shape)
+    got = h.vjp(u, w).cpu().numpy()
+    h.close()
+    jv = oracle.jvp_L(oracle.grid_from_spec(spec), u, v)
+    assert np.vdot(got, v) == pytest.approx(np.vdot(w, jv), rel=1e-11)
+
+
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("case", ["smooth_periodic", "smooth_outflow", "hubble", "hotspots"])
+def test_step_vjp_fp64_matches_oracle(case, order):
+    rh = rh_module()
+    spec = CASES[case](order)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP64)
+    dt, t = spec["dt"], spec["t0"]
+    got = h.step_vjp(u, w, dt, t=t).cpu().numpy()
+    h.close()
+    ref = oracle.vjp_step(oracle.grid_from_spec(spec), u, w, dt, t=t)
+    err = np.abs(got - ref).reshape(5, -1).max(axis=1) / np.abs(ref).max()
+    print(case, order, err, flush=True)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("case", ["smooth_periodic", "hotspots"])
+def test_vjp_fp32_close_to_oracle(case):
+    rh = rh_module()
+    spec = CASES[case](5)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP32)
+    dt = spec["dt"]
+    got = h.vjp(u, w).double().cpu().numpy()
+    gs = h.step_vjp(u, w, dt).double().cpu().numpy()
+    h.close()
+    u32 = u.astype(np.float32).astype(np.float64)
+    w32 = w.astype(np.float32).astype(np.float64)
+    g = oracle.grid_from_spec(spec)
+    err = vjp_errors(got, oracle.vjp_L(g, u32, w32), w32, min(spec["h"]))
+    ref_s = oracle.vjp_step(g, u32, w32, dt)
+    err_s = np.abs(gs - ref_s).max() / np.abs(ref_s).max()
+    print(case, "fp32", err, err_s, flush=True)
+    assert np.all(err <= 5e-5) and err_s <= 5e-5, (err, err_s)
+
+
+def test_charge_adjoint_is_zero_for_energy_momentum_weights():
+    rh = rh_module()
+    spec = CASES["hotspots"](5)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP64)
+    w[4] = 0.0
+    got = h.vjp(u, w).cpu().numpy()
+    h.close()
+    assert np.all(got[4] == 0.0)
