@@ -106,7 +106,8 @@ void rh_plan_destroy(rh_plan* plan);
 size_t rh_state_bytes(const rh_plan* plan);
 
 /* Bytes of the workspace the caller must provide to rh_bind: the two
- * intermediate Runge-Kutta stage states and the L accumulator (3 states). */
+ * intermediate Runge-Kutta stage states, the L accumulator and the recovered
+ * primitives of the current stage (4 state-sized slots). */
 size_t rh_workspace_bytes(const rh_plan* plan);
 
 /* Bind caller-owned device buffers and a stream.  state: rh_state_bytes bytes,
@@ -214,7 +215,7 @@ void rh_batch_destroy(rh_batch* batch);
  * concatenated buffer; offsets[n_grids] is the total element count. */
 rh_status rh_batch_offsets(const rh_batch* batch, long long* offsets);
 
-/* Bytes of the concatenated state, and of the workspace (3 such buffers). */
+/* Bytes of the concatenated state, and of the workspace (4 such buffers). */
 size_t rh_batch_state_bytes(const rh_batch* batch);
 size_t rh_batch_workspace_bytes(const rh_batch* batch);
 

@@ -122,6 +122,7 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
     a.dt = (T)dt;
     a.stage = stage;
     a.hb.t = t;
+    a.prims = (T*)p->ws + 3 * 5 * (size_t)p->ncell;   // the workspace's primitive slot
     const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
     const double h[3] = {p->d.dx, p->d.dy, p->d.dz};
     int active[3], na = 0;
@@ -139,6 +140,7 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
         const int d = active[i];
         rh::SweepArgs<T> b = a;
         b.first = i == 0;
+        b.prim_mode = i == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
         b.stage = i == na - 1 ? stage : rh::STAGE_WRITE_L;
         b.bc = p->d.bc[d];
         b.inv_h = (T)(1.0 / h[d]);
@@ -245,7 +247,7 @@ void rh_plan_destroy(rh_plan* p) {
 
 size_t rh_state_bytes(const rh_plan* p) { return p ? 5 * (size_t)p->ncell * p->elem : 0; }
 
-size_t rh_workspace_bytes(const rh_plan* p) { return p ? 3 * rh_state_bytes(p) : 0; }
+size_t rh_workspace_bytes(const rh_plan* p) { return p ? 4 * rh_state_bytes(p) : 0; }
 
 rh_status rh_bind(rh_plan* p, void* state, void* workspace, void* stream) {
     if (!p) return fail(RH_E_INVAL, "plan is NULL");
@@ -291,7 +293,7 @@ rh_status rh_apply_L(rh_plan* p, double t, void* L_out) {
     const char* lo = (const char*)L_out;
     const char* s0 = (const char*)p->state;
     const char* w0 = (const char*)p->ws;
-    if ((lo < s0 + sb && s0 < lo + sb) || (lo < w0 + 3 * sb && w0 < lo + sb))
+    if ((lo < s0 + sb && s0 < lo + sb) || (lo < w0 + 4 * sb && w0 < lo + sb))
         return fail(RH_E_INVAL, "L_out aliases the bound buffers");
     if (is_fp32(p))
         return evaluate<float>(p, (const float*)p->state, (const float*)p->state, (float*)L_out,
@@ -514,9 +516,11 @@ rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T
     B.base.hb.e0 = b->d[0].hubble_e0;
     B.base.hb.n0 = b->d[0].hubble_n0;
     B.base.clamps = b->d_clamps;
+    B.base.prims = (T*)b->ws + 3 * (size_t)b->off[b->ngrid];
     for (int d = 0; d < 3; ++d) {
         rh::BatchArgs<T> Bd = B;
         Bd.base.first = d == 0;
+        Bd.base.prim_mode = d == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
         Bd.base.stage = d == 2 ? stage : rh::STAGE_WRITE_L;
         rh_status st = batch_timed(b, s, RH_KERNEL_SWEEP_X + d, [&] {
             return rh::launch_sweep_batch<T>(d, b->scheme, b->tile_x, Bd, b->nblocks[d], s);
@@ -679,7 +683,7 @@ rh_status rh_batch_offsets(const rh_batch* b, long long* offsets) {
 
 size_t rh_batch_state_bytes(const rh_batch* b) { return b ? (size_t)b->off[b->ngrid] * b->elem : 0; }
 
-size_t rh_batch_workspace_bytes(const rh_batch* b) { return b ? 3 * rh_batch_state_bytes(b) : 0; }
+size_t rh_batch_workspace_bytes(const rh_batch* b) { return b ? 4 * rh_batch_state_bytes(b) : 0; }
 
 rh_status rh_batch_bind(rh_batch* b, void* state, void* workspace, void* stream) {
     if (!b) return fail(RH_E_INVAL, "batch is NULL");
@@ -830,6 +834,8 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
                 B.base.clamps = b->d_clamps;
                 B.base.first = 1;
                 B.base.stage = rh::STAGE_WRITE_L;
+                B.base.prims = (float*)b->ws + 3 * S;
+                B.base.prim_mode = cls == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
                 hipError_t er = rh::launch_sweep_batch<float>(cls, b->scheme, b->tile_x, B, b->nblocks[cls], b->stream);
                 return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
             }
@@ -845,6 +851,8 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
             B.base.clamps = b->d_clamps;
             B.base.first = 1;
             B.base.stage = rh::STAGE_WRITE_L;
+            B.base.prims = (double*)b->ws + 3 * S;
+            B.base.prim_mode = cls == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
             hipError_t er = rh::launch_sweep_batch<double>(cls, b->scheme, b->tile_x, B, b->nblocks[cls], b->stream);
             return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
         };
@@ -872,6 +880,10 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
         }
     }
     b->tile_x = best_tx;
+    if (rs == RH_OK && (rs = upload_table(b)) == RH_OK) {
+        float ms;
+        rs = time_class(0, &ms);   // fills the primitive slot the y and z timings load
+    }
     for (int d = 1; d < 3 && rs == RH_OK; ++d) {
         best_ms = 1e30f;
         for (int sg : {16, 32, 48, 64, 128}) {
@@ -1034,9 +1046,9 @@ rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const vo
         return fail(RH_E_INVAL, "scratch aliases an operand");
     if (overlaps(ubar_out, sb, u_n, sb)) return fail(RH_E_INVAL, "ubar_out aliases u_n");
     const char* ws = (const char*)p->ws;
-    if (overlaps(ws + 2 * sb, sb, u_n, sb) || overlaps(ws + 2 * sb, sb, ubar_in, sb) ||
-        overlaps(ws + 2 * sb, sb, ubar_out, sb) || overlaps(ws + 2 * sb, sb, scratch, 4 * sb))
-        return fail(RH_E_INVAL, "an operand aliases the bound workspace's L accumulator");
+    if (overlaps(ws + 2 * sb, 2 * sb, u_n, sb) || overlaps(ws + 2 * sb, 2 * sb, ubar_in, sb) ||
+        overlaps(ws + 2 * sb, 2 * sb, ubar_out, sb) || overlaps(ws + 2 * sb, 2 * sb, scratch, 4 * sb))
+        return fail(RH_E_INVAL, "an operand aliases the bound workspace's accumulator or primitives");
     return is_fp32(p) ? step_vjp_impl<float>(p, t, dt, (const float*)u_n, (const float*)ubar_in,
                                              (float*)ubar_out, (float*)scratch)
                       : step_vjp_impl<double>(p, t, dt, (const double*)u_n, (const double*)ubar_in,

@@ -222,7 +222,7 @@ class Hydro:
         nx, ny, nz = self.shape
         self.device = torch.device(device)
         self.state = torch.zeros((5, nz, ny, nx), dtype=self.dtype, device=self.device)
-        self.workspace = torch.zeros((3, 5, nz, ny, nx), dtype=self.dtype, device=self.device)
+        self.workspace = torch.zeros((4, 5, nz, ny, nx), dtype=self.dtype, device=self.device)
         assert self.state.numel() * self.state.element_size() == rh_state_bytes(self.plan)
         assert self.workspace.numel() * self.workspace.element_size() == rh_workspace_bytes(self.plan)
         self.t = float(t)
@@ -405,7 +405,7 @@ class Batch:
         self.dtype = torch.float32 if precision == RH_PREC_FP32 else torch.float64
         total = self.offsets[-1]
         self.state = torch.zeros(total, dtype=self.dtype, device=self.device)
-        self.workspace = torch.zeros(3 * total, dtype=self.dtype, device=self.device)
+        self.workspace = torch.zeros(4 * total, dtype=self.dtype, device=self.device)
         self.t = float(specs[0].get("t0", 0.0))
         rh_batch_bind(self.batch, self.state.data_ptr(), self.workspace.data_ptr(),
                       torch.cuda.current_stream(self.device).cuda_stream)
