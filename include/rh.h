@@ -175,11 +175,13 @@ rh_status rh_kernel_times(rh_plan* plan, double* ms_out, long long* launches_out
 
 /* out = J(u)^T w, J = dL/du of Eq. (2) at state u and time t.  u, w and out are
  * device buffers of the plan precision and layout [5][nz][ny][nx]; out must
- * not alias u or w.  The plan need not be bound; work goes to the bound stream
- * (or the default stream if unbound).  Errors: RH_E_INVAL (NULL or aliasing). */
+ * not alias u or w, and none of them may alias the bound workspace, whose
+ * contents this call overwrites (it holds x-y transposed copies for the x
+ * axis).  Asynchronous on the bound stream.  Errors: RH_E_STATE (unbound),
+ * RH_E_INVAL (NULL or aliasing). */
 rh_status rh_apply_vjp(rh_plan* plan, double t, const void* u, const void* w, void* out);
 
-/* Bytes of the scratch buffer rh_step_vjp needs (four states). */
+/* Bytes of the scratch buffer rh_step_vjp needs (three states). */
 size_t rh_vjp_workspace_bytes(const rh_plan* plan);
 
 /* Adjoint of one SSP-RK3 step taken from u_n at time t with step dt:
@@ -187,9 +189,10 @@ size_t rh_vjp_workspace_bytes(const rh_plan* plan);
  * recomputed into scratch (rh_vjp_workspace_bytes), then
  *   b2 = 2/3 b + 2/3 dt J(u2)^T b,  b1 = 1/4 b2 + 1/4 dt J(u1)^T b2,
  *   ubar_out = 1/3 b + 3/4 b2 + b1 + dt J(u_n)^T b1   (b = ubar_in),
- * with J(u2) at t + dt/2, J(u1) at t + dt, J(u_n) at t.  The plan must be bound
- * (its workspace holds the L accumulator of the recomputation).  ubar_out may
- * alias ubar_in.  Errors: RH_E_STATE (unbound), RH_E_INVAL. */
+ * with J(u2) at t + dt/2, J(u1) at t + dt, J(u_n) at t.  The plan must be bound;
+ * its workspace is overwritten (recomputation and transposed copies) and may
+ * not alias any operand.  ubar_out may alias ubar_in.  Errors: RH_E_STATE
+ * (unbound), RH_E_INVAL. */
 rh_status rh_step_vjp(rh_plan* plan, double t, double dt, const void* u_n, const void* ubar_in,
                       void* ubar_out, void* scratch);
 

@@ -109,15 +109,31 @@ __device__ __forceinline__ void adj_weight(const AdjArgs<T>& A, const Column<T, 
 
 }  // namespace
 
-template <class T, int ORDER, int DIR>
-__global__ void __launch_bounds__(256) adj_roll(AdjArgs<T> A) {
-    constexpr int R = (ORDER + 1) / 2, W = 2 * R;
-    Column<T, DIR> C;
-    if (!column_of<T, DIR>(A, blockIdx.x * 256u + threadIdx.x, C)) return;
+// The WENO reconstruction is component-wise, so the face gradients of each
+// conserved component need only that component's window; the components are
+// therefore processed in groups, one pass per group over the lane's segment,
+// each pass carrying only its group's window (which keeps the register file
+// small enough for several waves per SIMD).  A pass adds its group's part of
+// (d f+/du)^T a+ + (d f-/du)^T a- to every field of the owned cells.
+//
+// Components per pass: FP32 WENO5 3 (passes {0,1,2}, {3,4}); otherwise 2.
+#ifndef RH_ADJ_GROUP_F32_W5
+#define RH_ADJ_GROUP_F32_W5 3
+#endif
+#ifndef RH_ADJ_GROUP_OTHER
+#define RH_ADJ_GROUP_OTHER 2
+#endif
+
+template <class T, int ORDER>
+struct AdjGroup {
+    static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? RH_ADJ_GROUP_F32_W5 : RH_ADJ_GROUP_OTHER;
+};
+
+template <class T, int ORDER, int DIR, int CLO, int CHI>
+__device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
+    constexpr int R = (ORDER + 1) / 2, W = 2 * R, NC = CHI - CLO;
     const int nd = A.n[DIR];
     const bool periodic = A.bc == RH_BC_PERIODIC;
-    const int k0 = blockIdx.y * A.seg;
-    const int k1 = min(k0 + A.seg, nd);
     int i_lo = k0 - R, i_hi = k1 + R - 2;
     if (!periodic) {
         i_lo = max(i_lo, -1);
@@ -127,100 +143,253 @@ __global__ void __launch_bounds__(256) adj_roll(AdjArgs<T> A) {
     const int own_lo = (!periodic && k0 == 0 && A.bc == RH_BC_OUTFLOW) ? -(1 << 30) : k0;
     const int own_hi = (!periodic && k1 == nd && A.bc == RH_BC_OUTFLOW) ? (1 << 30) : k1;
     const T eps = A.eps;
+    const T half = (T)0.5;
+    unsigned dummy = 0;
 
-    auto finalize = [&](int pos, const T ap[5], const T am[5]) {
-        if (pos < own_lo || pos >= own_hi) return;
-        int tgt = pos;
+    // split fluxes of the group's components from a cell state
+    auto group_flux = [&](const T u[5], T fp[NC], T fm[NC]) {
+        double vd = 0.0, pd = 0.0;
+        if constexpr (CHI > 1) recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, pd, dummy);
+        const T v = (T)vd, P = (T)pd;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int c = CLO + q;
+            T f;
+            if (c == 0) f = u[1 + DIR];
+            else if (c == 4) f = u[4] * v;
+            else f = u[c] * v + (c == 1 + DIR ? P : (T)0);
+            fp[q] = half * (f + u[c]);
+            fm[q] = half * (f - u[c]);
+        }
+    };
+    // Owned position pos -> the cell whose adjoint it updates (outflow ghost
+    // positions fold onto the edge cell; analytic ghosts are constants).
+    auto target = [&](int pos, int& tgt) -> bool {
+        if (pos < own_lo || pos >= own_hi) return false;
+        tgt = pos;
         if (pos < 0 || pos >= nd) {
-            if (A.bc != RH_BC_OUTFLOW) return;   // analytic ghosts are constants
+            if (A.bc != RH_BC_OUTFLOW) return false;
             tgt = pos < 0 ? 0 : nd - 1;
         }
-        T u[5], ub[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
-        adj_load<T, DIR>(A, C, tgt, u);
-        split_flux_vjp<T, DIR>(u, ap, am, ub);
+        return true;
+    };
+    // state and running adjoint of the cell updated next; consecutive updates
+    // of one cell (outflow edges) continue from registers
+    int last_tgt = -1;
+    T ubo[5], uf[5];
+    auto fetch_cell = [&](int tgt) {
         const long long id = C.base + (long long)tgt * C.stride;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) A.ub[f * A.fstride + id] += ub[f];
+        for (int f = 0; f < 5; ++f) uf[f] = A.u[f * A.fstride + id];
+        if (tgt == last_tgt) return;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) ubo[f] = A.ub[f * A.fstride + id];
+    };
+    // ub += scale * sum over the group of (d f+_c/du)^T a+_c + (d f-_c/du)^T a-_c
+    auto finish = [&](int tgt, const T apj[NC], const T amj[NC]) {
+        double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            lam[CLO + q] = 0.5 * ((double)apj[q] + (double)amj[q]);
+            dl[CLO + q] = 0.5 * ((double)apj[q] - (double)amj[q]);
+        }
+        double g[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g[c] = dl[c];
+        g[1 + DIR] += lam[0];
+        if constexpr (CHI > 1) {
+            double vd, pd, gv[4], gp[4];
+            recover_vp_grad<DIR>((double)uf[0], (double)uf[1], (double)uf[2], (double)uf[3], vd, pd, gv, gp);
+            // F_c = M_c v + p delta(c, 1+DIR) (c = 1..3), F_4 = N v
+            double S = 0.0;
+#pragma unroll
+            for (int c = (CLO > 1 ? CLO : 1); c < CHI; ++c) {
+                S += lam[c] * (double)uf[c];
+                g[c] += lam[c] * vd;
+            }
+            const double lp = lam[1 + DIR];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) g[m] += S * gv[m] + lp * gp[m];
+        }
+        const long long id = C.base + (long long)tgt * C.stride;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            ubo[f] = ubo[f] + A.scale * (T)g[f];
+            A.ub[f * A.fstride + id] = ubo[f];
+        }
+        last_tgt = tgt;
     };
 
-    T wp[5][W], wm[5][W], ap[5][W], am[5][W];
-    unsigned dummy = 0;
+    T wp[NC][W], wm[NC][W], ap[NC][W], am[NC][W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        T u[5], fp[5], fm[5];
+        T u[5], fp[NC], fm[NC];
         adj_load<T, DIR>(A, C, i_lo - R + 1 + j, u);
-        split_flux<T, DIR>(u, fp, fm, dummy);
+        group_flux(u, fp, fm);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            wp[c][j] = fp[c];
-            wm[c][j] = fm[c];
-            ap[c][j] = (T)0;
-            am[c][j] = (T)0;
+        for (int q = 0; q < NC; ++q) {
+            wp[q][j] = fp[q];
+            wm[q][j] = fm[q];
+            ap[q][j] = (T)0;
+            am[q][j] = (T)0;
         }
     }
-    T wl[5];
-    adj_weight<T, DIR>(A, C, i_lo, wl);
-    for (int i = i_lo; i <= i_hi; ++i) {
-        T wr[5];
-        adj_weight<T, DIR>(A, C, i + 1, wr);
+    // loads run one face ahead: the weights of the next face's right cell and
+    // the state of the next cell to enter the window are in flight while this
+    // face is differentiated (positions past the segment stay in bounds)
+    T wl[NC], wn[NC], un[5];
+    {
+        T w5[5];
+        adj_weight<T, DIR>(A, C, i_lo, w5);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            const T g = (wr[c] - wl[c]) * A.inv_h;
-            wl[c] = wr[c];
+        for (int q = 0; q < NC; ++q) wl[q] = w5[CLO + q];
+        adj_weight<T, DIR>(A, C, i_lo + 1, w5);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
+    }
+    adj_load<T, DIR>(A, C, i_lo + R + 1, un);
+    for (int i = i_lo; i <= i_hi; ++i) {
+        T wr[NC], unew[5];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) wr[q] = wn[q];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) unew[f] = un[f];
+        {
+            T w5[5];
+            adj_weight<T, DIR>(A, C, i + 2, w5);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
+        }
+        adj_load<T, DIR>(A, C, i + R + 2, un);
+        int tgt = 0;
+        const bool own = target(i - R + 1, tgt);
+        if (own) fetch_cell(tgt);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const T g = (wr[q] - wl[q]) * A.inv_h;
+            wl[q] = wr[q];
             if constexpr (ORDER == 5) {
-                weno5_grad_acc<T>(wp[c][0], wp[c][1], wp[c][2], wp[c][3], wp[c][4], (T)4 * eps, g,
-                                  ap[c][0], ap[c][1], ap[c][2], ap[c][3], ap[c][4]);
-                weno5_grad_acc<T>(wm[c][5], wm[c][4], wm[c][3], wm[c][2], wm[c][1], (T)4 * eps, g,
-                                  am[c][5], am[c][4], am[c][3], am[c][2], am[c][1]);
+                weno5_grad_acc<T>(wp[q][0], wp[q][1], wp[q][2], wp[q][3], wp[q][4], (T)4 * eps, g,
+                                  ap[q][0], ap[q][1], ap[q][2], ap[q][3], ap[q][4]);
+                weno5_grad_acc<T>(wm[q][5], wm[q][4], wm[q][3], wm[q][2], wm[q][1], (T)4 * eps, g,
+                                  am[q][5], am[q][4], am[q][3], am[q][2], am[q][1]);
             } else {
-                T s[7], o[7];
-                for (int j = 0; j < 7; ++j) { s[j] = wp[c][j]; o[j] = (T)0; }
-                weno7_grad_acc<T>(s, eps, g, o);
-                for (int j = 0; j < 7; ++j) ap[c][j] += o[j];
-                for (int j = 0; j < 7; ++j) { s[j] = wm[c][7 - j]; o[j] = (T)0; }
-                weno7_grad_acc<T>(s, eps, g, o);
-                for (int j = 0; j < 7; ++j) am[c][7 - j] += o[j];
+                T sv[7], o[7];
+#pragma unroll
+                for (int j = 0; j < 7; ++j) { sv[j] = wp[q][j]; o[j] = (T)0; }
+                weno7_grad_acc<T>(sv, eps, g, o);
+#pragma unroll
+                for (int j = 0; j < 7; ++j) ap[q][j] += o[j];
+#pragma unroll
+                for (int j = 0; j < 7; ++j) { sv[j] = wm[q][7 - j]; o[j] = (T)0; }
+                weno7_grad_acc<T>(sv, eps, g, o);
+#pragma unroll
+                for (int j = 0; j < 7; ++j) am[q][7 - j] += o[j];
             }
         }
-        {
-            T a0p[5], a0m[5];
+        if (own) {
+            T a0p[NC], a0m[NC];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                a0p[c] = ap[c][0];
-                a0m[c] = am[c][0];
+            for (int q = 0; q < NC; ++q) {
+                a0p[q] = ap[q][0];
+                a0m[q] = am[q][0];
             }
-            finalize(i - R + 1, a0p, a0m);
+            finish(tgt, a0p, a0m);
         }
         if (i < i_hi) {
-            T u[5], fp[5], fm[5];
-            adj_load<T, DIR>(A, C, i + R + 1, u);
-            split_flux<T, DIR>(u, fp, fm, dummy);
+            T fp[NC], fm[NC];
+            group_flux(unew, fp, fm);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
+            for (int q = 0; q < NC; ++q) {
 #pragma unroll
                 for (int j = 0; j < W - 1; ++j) {
-                    wp[c][j] = wp[c][j + 1];
-                    wm[c][j] = wm[c][j + 1];
-                    ap[c][j] = ap[c][j + 1];
-                    am[c][j] = am[c][j + 1];
+                    wp[q][j] = wp[q][j + 1];
+                    wm[q][j] = wm[q][j + 1];
+                    ap[q][j] = ap[q][j + 1];
+                    am[q][j] = am[q][j + 1];
                 }
-                wp[c][W - 1] = fp[c];
-                wm[c][W - 1] = fm[c];
-                ap[c][W - 1] = (T)0;
-                am[c][W - 1] = (T)0;
+                wp[q][W - 1] = fp[q];
+                wm[q][W - 1] = fm[q];
+                ap[q][W - 1] = (T)0;
+                am[q][W - 1] = (T)0;
             }
         }
     }
     // positions still in the window after the last face
 #pragma unroll
     for (int j = 1; j < W; ++j) {
-        T ajp[5], ajm[5];
+        int tgt = 0;
+        if (!target(i_hi - R + 1 + j, tgt)) continue;
+        fetch_cell(tgt);
+        T ajp[NC], ajm[NC];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            ajp[c] = ap[c][j];
-            ajm[c] = am[c][j];
+        for (int q = 0; q < NC; ++q) {
+            ajp[q] = ap[q][j];
+            ajm[q] = am[q][j];
         }
-        finalize(i_hi - R + 1 + j, ajp, ajm);
+        finish(tgt, ajp, ajm);
+    }
+}
+
+template <class T, int ORDER, int DIR, int CLO>
+__device__ __forceinline__ void adj_passes(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
+    if constexpr (CLO < 5) {
+        constexpr int GS = AdjGroup<T, ORDER>::value;
+        constexpr int CHI = CLO + GS < 5 ? CLO + GS : 5;
+        adj_pass<T, ORDER, DIR, CLO, CHI>(A, C, k0, k1);
+        adj_passes<T, ORDER, DIR, CHI>(A, C, k0, k1);
+    }
+}
+
+#ifndef RH_ADJ_MINB
+#define RH_ADJ_MINB 1
+#endif
+
+template <class T, int ORDER, int DIR>
+__global__ void __launch_bounds__(256, RH_ADJ_MINB) adj_roll(AdjArgs<T> A) {
+    Column<T, DIR> C;
+    if (!column_of<T, DIR>(A, blockIdx.x * 256u + threadIdx.x, C)) return;
+    const int k0 = blockIdx.y * A.seg;
+    const int k1 = min(k0 + A.seg, A.n[DIR]);
+    adj_passes<T, ORDER, DIR, 0>(A, C, k0, k1);
+}
+
+// Square tiles of 256-byte rows through LDS (64 x 64 FP32, 32 x 32 FP64), so
+// that every read and write of a wave is a contiguous 256-byte run.  init may
+// alias out (each element is read and written by the same lane).
+template <class T>
+struct TransposeTile {
+    static constexpr int value = 256 / sizeof(T);
+};
+
+template <class T, bool INIT>
+__global__ void __launch_bounds__(256) transpose_xy(const T* __restrict__ in, T* out, int R, int C, int nz,
+                                                    long long fs, T a, const T* init, T s) {
+    constexpr int TS = TransposeTile<T>::value, RS = 256 / TS;
+    __shared__ T tile[TS][TS + 1];
+    const int z = blockIdx.z % nz, f = blockIdx.z / nz;
+    const int fo = f == 1 ? 2 : (f == 2 ? 1 : f);
+    const long long plane = (long long)R * C;
+    const T* src = in + f * fs + z * plane;
+    const long long dbase = fo * fs + z * plane;
+    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+    const int c0 = blockIdx.x * TS, r0 = blockIdx.y * TS;
+#pragma unroll
+    for (int kk = 0; kk < TS / RS; ++kk) {
+        const int k = ty + kk * RS;
+        const int r = r0 + k, c = c0 + tx;
+        if (r < R && c < C) tile[k][tx] = src[(long long)r * C + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TS / RS; ++kk) {
+        const int k = ty + kk * RS;
+        const int c = c0 + k, r = r0 + tx;   // output row c, column r
+        if (r < R && c < C) {
+            const long long o = dbase + (long long)c * R + r;
+            const T v = s * tile[tx][k];
+            out[o] = INIT ? a * init[o] + v : v;
+        }
     }
 }
 
@@ -262,15 +431,25 @@ hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s)
     a.seg = choose_segment(nd, (int)(gx * 256));
     const unsigned gy = (nd + a.seg - 1) / a.seg;
     const dim3 grid(gx, gy), block(256);
+    if (dir != 1 && dir != 2) return hipErrorInvalidValue;
     if (order == 5) {
-        if (dir == 0) adj_roll<T, 5, 0><<<grid, block, 0, s>>>(a);
-        else if (dir == 1) adj_roll<T, 5, 1><<<grid, block, 0, s>>>(a);
+        if (dir == 1) adj_roll<T, 5, 1><<<grid, block, 0, s>>>(a);
         else adj_roll<T, 5, 2><<<grid, block, 0, s>>>(a);
     } else {
-        if (dir == 0) adj_roll<T, 7, 0><<<grid, block, 0, s>>>(a);
-        else if (dir == 1) adj_roll<T, 7, 1><<<grid, block, 0, s>>>(a);
+        if (dir == 1) adj_roll<T, 7, 1><<<grid, block, 0, s>>>(a);
         else adj_roll<T, 7, 2><<<grid, block, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_transpose_xy(const T* in, T* out, int R, int C, int nz, long long fs, T a, const T* init,
+                               T s, hipStream_t st) {
+    constexpr int TS = TransposeTile<T>::value;
+    if ((long long)5 * nz > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((C + TS - 1) / TS), (unsigned)((R + TS - 1) / TS), (unsigned)(5 * nz));
+    if (init) transpose_xy<T, true><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, a, init, s);
+    else transpose_xy<T, false><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, a, init, s);
     return hipGetLastError();
 }
 
@@ -290,6 +469,8 @@ hipError_t launch_lincomb(T* out, long long n, T a, const T* X, T b, const T* Y,
 #define RH_ADJ_INSTANTIATE(T)                                                                      \
     template hipError_t launch_adjoint_sweep<T>(int, int, AdjArgs<T>, hipStream_t);               \
     template hipError_t launch_fill_zero<T>(T*, long long, hipStream_t);                          \
+    template hipError_t launch_transpose_xy<T>(const T*, T*, int, int, int, long long, T, const T*, T, \
+                                               hipStream_t);                                       \
     template hipError_t launch_lincomb<T>(T*, long long, T, const T*, T, const T*, T, const T*, T, \
                                           const T*, hipStream_t);
 

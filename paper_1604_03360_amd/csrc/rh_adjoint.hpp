@@ -160,18 +160,21 @@ __device__ __forceinline__ void recover_vp_grad(double E, double Mx, double My, 
     }
     const double D = sqrt(4.0 * E * E - 3.0 * M2);
     const double a = 2.0 * E + D, b = E + D;
-    const double k = 3.0 / a;
+    // 1/a, 1/b and 1/D from one refined reciprocal of a b D (D >= E > 0 here)
+    const double r = fast_rcp(a * b * D);
+    const double ra = b * D * r, rb = a * D * r, rD = a * b * r;
+    const double k = 3.0 * ra;
     vd = k * Me[DIR];
-    p = (E * E - M2) / b;
+    p = (E * E - M2) * rb;
     // gradients with respect to (E, Me)
-    const double dk_dE = -(k / a) * (2.0 + 4.0 * E / D);
+    const double dk_dE = -(k * ra) * (2.0 + 4.0 * E * rD);
     double gve[4], gpe[4];
     gve[0] = Me[DIR] * dk_dE;
-    gpe[0] = (2.0 * E - p * (1.0 + 4.0 * E / D)) / b;
+    gpe[0] = (2.0 * E - p * (1.0 + 4.0 * E * rD)) * rb;
+    const double kk = 3.0 * k * ra * rD, pp = (3.0 * p * rD - 2.0) * rb;
     for (int i = 0; i < 3; ++i) {
-        const double dk_dM = 3.0 * k * Me[i] / (a * D);
-        gve[1 + i] = (i == DIR ? k : 0.0) + Me[DIR] * dk_dM;
-        gpe[1 + i] = Me[i] * (3.0 * p / D - 2.0) / b;
+        gve[1 + i] = (i == DIR ? k : 0.0) + Me[DIR] * (kk * Me[i]);
+        gpe[1 + i] = Me[i] * pp;
     }
     if (!capped) {
         for (int q = 0; q < 4; ++q) {

@@ -941,40 +941,93 @@ rh_status rh_batch_kernel_times(rh_batch* b, double* ms_out, long long* launches
 // ===========================================================================
 namespace {
 
+// out = a init + s J(u)^T w (init may be null, meaning 0, and may alias out).
+// The x axis runs as a y sweep on x-y transposed copies of u and w (momentum
+// fields exchanged), so that its loads are coalesced; the transposed adjoint is
+// added back by the transpose that initialises out.  The bound workspace's
+// first three slots hold the transposed u, w and adjoint.
 template <class T>
-rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out) {
+rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, T a, const T* init, T s) {
     const long long N = 5 * p->ncell;
-    rh_status st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(out, N, p->stream); },
-                                "fill launch");
-    if (st != RH_OK) return st;
     const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
     const double h[3] = {p->d.dx, p->d.dy, p->d.dz};
-    for (int d = 0; d < 3; ++d) {
-        if (n[d] < 2) continue;   // a one-cell axis contributes nothing to L
-        rh::AdjArgs<T> a;
-        std::memset(&a, 0, sizeof(a));
-        a.u = u;
-        a.w = w;
-        a.ub = out;
-        a.fstride = p->ncell;
-        a.n[0] = n[0];
-        a.n[1] = n[1];
-        a.n[2] = n[2];
-        a.bc = p->d.bc[d];
-        a.inv_h = (T)(1.0 / h[d]);
-        a.eps = (T)(p->d.weno_eps > 0.0 ? p->d.weno_eps : 1e-6);
-        a.hb.t = t;
-        a.hb.t0 = p->d.hubble_t0;
-        a.hb.e0 = p->d.hubble_e0;
-        a.hb.n0 = p->d.hubble_n0;
-        a.hb.c0[0] = p->d.x0;
-        a.hb.c0[1] = p->d.y0;
-        a.hb.c0[2] = p->d.z0;
-        a.hb.h[0] = h[0];
-        a.hb.h[1] = h[1];
-        a.hb.h[2] = h[2];
+    rh::AdjArgs<T> base;
+    std::memset(&base, 0, sizeof(base));
+    base.fstride = p->ncell;
+    base.eps = (T)(p->d.weno_eps > 0.0 ? p->d.weno_eps : 1e-6);
+    base.hb.t = t;
+    base.hb.t0 = p->d.hubble_t0;
+    base.hb.e0 = p->d.hubble_e0;
+    base.hb.n0 = p->d.hubble_n0;
+    rh_status st = RH_OK;
+    if (n[0] > 1) {
+        T* uT = (T*)p->ws;
+        T* wT = uT + N;
+        T* bT = uT + 2 * N;
+        auto tr = [&](const T* in, T* o, int R, int C, T aa, const T* ini, T ss) {
+            return timed_launch(p, RH_KERNEL_OTHER, [&] {
+                return rh::launch_transpose_xy<T>(in, o, R, C, n[2], p->ncell, aa, ini, ss, p->stream);
+            }, "transpose launch");
+        };
+        if ((st = tr(u, uT, n[1], n[0], (T)0, nullptr, (T)1)) != RH_OK) return st;
+        if ((st = tr(w, wT, n[1], n[0], (T)0, nullptr, (T)1)) != RH_OK) return st;
+        st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(bT, N, p->stream); },
+                          "fill launch");
+        if (st != RH_OK) return st;
+        rh::AdjArgs<T> x = base;
+        x.u = uT;
+        x.w = wT;
+        x.ub = bT;
+        x.n[0] = n[1];
+        x.n[1] = n[0];
+        x.n[2] = n[2];
+        x.bc = p->d.bc[0];
+        x.inv_h = (T)(1.0 / h[0]);
+        x.scale = (T)1;
+        x.hb.c0[0] = p->d.y0;
+        x.hb.c0[1] = p->d.x0;
+        x.hb.c0[2] = p->d.z0;
+        x.hb.h[0] = h[1];
+        x.hb.h[1] = h[0];
+        x.hb.h[2] = h[2];
         st = timed_launch(p, RH_KERNEL_ADJOINT,
-                          [&] { return rh::launch_adjoint_sweep<T>(d, p->d.scheme, a, p->stream); },
+                          [&] { return rh::launch_adjoint_sweep<T>(1, p->d.scheme, x, p->stream); },
+                          "adjoint sweep launch");
+        if (st != RH_OK) return st;
+        if ((st = tr(bT, out, n[0], n[1], a, init, s)) != RH_OK) return st;
+    } else if (init) {
+        if (init != out || a != (T)1) {
+            st = timed_launch(p, RH_KERNEL_OTHER, [&] {
+                return rh::launch_lincomb<T>(out, N, a, init, (T)0, nullptr, (T)0, nullptr, (T)0, nullptr,
+                                             p->stream);
+            }, "combine launch");
+            if (st != RH_OK) return st;
+        }
+    } else {
+        st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(out, N, p->stream); },
+                          "fill launch");
+        if (st != RH_OK) return st;
+    }
+    for (int d = 1; d < 3; ++d) {
+        if (n[d] < 2) continue;   // a one-cell axis contributes nothing to L
+        rh::AdjArgs<T> q = base;
+        q.u = u;
+        q.w = w;
+        q.ub = out;
+        q.n[0] = n[0];
+        q.n[1] = n[1];
+        q.n[2] = n[2];
+        q.bc = p->d.bc[d];
+        q.inv_h = (T)(1.0 / h[d]);
+        q.scale = s;
+        q.hb.c0[0] = p->d.x0;
+        q.hb.c0[1] = p->d.y0;
+        q.hb.c0[2] = p->d.z0;
+        q.hb.h[0] = h[0];
+        q.hb.h[1] = h[1];
+        q.hb.h[2] = h[2];
+        st = timed_launch(p, RH_KERNEL_ADJOINT,
+                          [&] { return rh::launch_adjoint_sweep<T>(d, p->d.scheme, q, p->stream); },
                           "adjoint sweep launch");
         if (st != RH_OK) return st;
     }
@@ -987,29 +1040,24 @@ rh_status step_vjp_impl(rh_plan* p, double t, double dt, const T* un, const T* b
     T* u1 = scratch;
     T* u2 = scratch + S;
     T* b2 = scratch + 2 * S;
-    T* tmp = scratch + 3 * S;
     T* Lc = (T*)p->ws + 2 * S;   // the bound workspace's L accumulator
     rh_status st = evaluate<T>(p, un, un, Lc, u1, t, dt, rh::STAGE_1);
     if (st == RH_OK) st = evaluate<T>(p, u1, un, Lc, u2, t + dt, dt, rh::STAGE_2);
     if (st != RH_OK) return st;
-    const long long N = (long long)S;
     const T td = (T)dt;
-    auto lin = [&](T* out, T a, const T* X, T b, const T* Y, T c, const T* Z, T d, const T* V) {
-        return timed_launch(p, RH_KERNEL_OTHER,
-                            [&] { return rh::launch_lincomb<T>(out, N, a, X, b, Y, c, Z, d, V, p->stream); },
-                            "combine launch");
-    };
     // b2 = 2/3 b + 2/3 dt J(u2)^T b
-    if ((st = vjp_impl<T>(p, t + 0.5 * dt, u2, bin, tmp)) != RH_OK) return st;
-    if ((st = lin(b2, (T)(2.0 / 3.0), bin, (T)(2.0 / 3.0) * td, tmp, (T)0, nullptr, (T)0, nullptr)) != RH_OK)
+    if ((st = vjp_impl<T>(p, t + 0.5 * dt, u2, bin, b2, (T)(2.0 / 3.0), bin, (T)(2.0 / 3.0) * td)) != RH_OK)
         return st;
     // b1 = 1/4 b2 + 1/4 dt J(u1)^T b2   (b1 stored in u2's slot, u2 no longer needed)
     T* b1 = u2;
-    if ((st = vjp_impl<T>(p, t + dt, u1, b2, tmp)) != RH_OK) return st;
-    if ((st = lin(b1, (T)0.25, b2, (T)0.25 * td, tmp, (T)0, nullptr, (T)0, nullptr)) != RH_OK) return st;
-    // out = 1/3 b + 3/4 b2 + b1 + dt J(un)^T b1
-    if ((st = vjp_impl<T>(p, t, un, b1, tmp)) != RH_OK) return st;
-    return lin(bout, (T)(1.0 / 3.0), bin, (T)0.75, b2, (T)1, b1, td, tmp);
+    if ((st = vjp_impl<T>(p, t + dt, u1, b2, b1, (T)0.25, b2, (T)0.25 * td)) != RH_OK) return st;
+    // out = (1/3 b + 3/4 b2 + b1) + dt J(un)^T b1
+    st = timed_launch(p, RH_KERNEL_OTHER, [&] {
+        return rh::launch_lincomb<T>(bout, (long long)S, (T)(1.0 / 3.0), bin, (T)0.75, b2, (T)1, b1, (T)0,
+                                     nullptr, p->stream);
+    }, "combine launch");
+    if (st != RH_OK) return st;
+    return vjp_impl<T>(p, t, un, b1, bout, (T)1, bout, td);
 }
 
 // [a, a + na) and [b, b + nb) intersect
@@ -1024,15 +1072,19 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 extern "C" {
 
 rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void* out) {
-    if (!p) return fail(RH_E_INVAL, "plan is NULL");
+    rh_status st = check_bound(p);
+    if (st != RH_OK) return st;
     if (!u || !w || !out) return fail(RH_E_INVAL, "NULL buffer");
     const size_t sb = rh_state_bytes(p);
     if (overlaps(out, sb, u, sb) || overlaps(out, sb, w, sb)) return fail(RH_E_INVAL, "out aliases u or w");
-    return is_fp32(p) ? vjp_impl<float>(p, t, (const float*)u, (const float*)w, (float*)out)
-                      : vjp_impl<double>(p, t, (const double*)u, (const double*)w, (double*)out);
+    if (overlaps(p->ws, 4 * sb, u, sb) || overlaps(p->ws, 4 * sb, w, sb) || overlaps(p->ws, 4 * sb, out, sb))
+        return fail(RH_E_INVAL, "an operand aliases the bound workspace");
+    return is_fp32(p) ? vjp_impl<float>(p, t, (const float*)u, (const float*)w, (float*)out, 0.0f, nullptr, 1.0f)
+                      : vjp_impl<double>(p, t, (const double*)u, (const double*)w, (double*)out, 0.0, nullptr,
+                                         1.0);
 }
 
-size_t rh_vjp_workspace_bytes(const rh_plan* p) { return p ? 4 * rh_state_bytes(p) : 0; }
+size_t rh_vjp_workspace_bytes(const rh_plan* p) { return p ? 3 * rh_state_bytes(p) : 0; }
 
 rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const void* ubar_in,
                       void* ubar_out, void* scratch) {
@@ -1041,14 +1093,14 @@ rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const vo
     if (!u_n || !ubar_in || !ubar_out || !scratch) return fail(RH_E_INVAL, "NULL buffer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
     const size_t sb = rh_state_bytes(p);
-    if (overlaps(scratch, 4 * sb, u_n, sb) || overlaps(scratch, 4 * sb, ubar_in, sb) ||
-        overlaps(scratch, 4 * sb, ubar_out, sb))
+    if (overlaps(scratch, 3 * sb, u_n, sb) || overlaps(scratch, 3 * sb, ubar_in, sb) ||
+        overlaps(scratch, 3 * sb, ubar_out, sb))
         return fail(RH_E_INVAL, "scratch aliases an operand");
     if (overlaps(ubar_out, sb, u_n, sb)) return fail(RH_E_INVAL, "ubar_out aliases u_n");
     const char* ws = (const char*)p->ws;
-    if (overlaps(ws + 2 * sb, 2 * sb, u_n, sb) || overlaps(ws + 2 * sb, 2 * sb, ubar_in, sb) ||
-        overlaps(ws + 2 * sb, 2 * sb, ubar_out, sb) || overlaps(ws + 2 * sb, 2 * sb, scratch, 4 * sb))
-        return fail(RH_E_INVAL, "an operand aliases the bound workspace's accumulator or primitives");
+    if (overlaps(ws, 4 * sb, u_n, sb) || overlaps(ws, 4 * sb, ubar_in, sb) ||
+        overlaps(ws, 4 * sb, ubar_out, sb) || overlaps(ws, 4 * sb, scratch, 3 * sb))
+        return fail(RH_E_INVAL, "an operand aliases the bound workspace");
     return is_fp32(p) ? step_vjp_impl<float>(p, t, dt, (const float*)u_n, (const float*)ubar_in,
                                              (float*)ubar_out, (float*)scratch)
                       : step_vjp_impl<double>(p, t, dt, (const double*)u_n, (const double*)ubar_in,

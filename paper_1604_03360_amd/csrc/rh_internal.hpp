@@ -69,11 +69,19 @@ struct AdjArgs {
     int seg;            // owned segment length along the axis
     T inv_h;
     T eps;
+    T scale;            // ub += scale * (J^T w) of this axis
     HubbleBC hb;
 };
 
+// dir is 1 (y) or 2 (z); the x axis runs as a y sweep on x-y transposed copies
 template <class T>
 hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s);
+// Per z-plane transpose of a [5][nz][R][C] field set into [5][nz][C][R] with the
+// two in-plane momentum fields (1 and 2) exchanged.  With init non-null the
+// result is out = a init + s transpose(in), else out = s transpose(in).
+template <class T>
+hipError_t launch_transpose_xy(const T* in, T* out, int R, int C, int nz, long long fstride, T a,
+                               const T* init, T s, hipStream_t st);
 template <class T>
 hipError_t launch_fill_zero(T* p, long long n, hipStream_t s);
 template <class T>

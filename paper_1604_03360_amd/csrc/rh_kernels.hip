@@ -232,6 +232,11 @@ __device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
     *(T*)((char*)base + off) = v;
 }
 
+// Cells each rolling lane keeps in flight ahead of the one it computes.
+#ifndef RH_ROLL_PREFETCH
+#define RH_ROLL_PREFETCH 1
+#endif
+
 // bx: 256-lane chunk of the (x, w) plane; by: segment along the sweep axis
 template <class T, int ORDER, int DIR>
 __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned bx, int by) {
@@ -286,14 +291,26 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
     for (int c = 0; c < 5; ++c)
         Fl[c] = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
 
-    T nxt[5], nv, nP;
-    fetch(k0 + R, nxt, nv, nP);
+    // cells k+R .. k+R+PF-1 are in flight while iteration k computes
+    constexpr int PF = RH_ROLL_PREFETCH;
+    T nxt[PF][5], nv[PF], nP[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) fetch(k0 + R + j, nxt[j], nv[j], nP[j]);
     for (int k = k0; k < kend; ++k) {
         T u[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) u[f] = nxt[f];
-        const T v = nv, P = nP;
-        fetch(k + 1 + R, nxt, nv, nP);   // next iteration's new cell, in flight during this one
+        for (int f = 0; f < 5; ++f) u[f] = nxt[0][f];
+        const T v = nv[0], P = nP[0];
+#pragma unroll
+        for (int j = 0; j + 1 < PF; ++j) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) nxt[j][f] = nxt[j + 1][f];
+            nv[j] = nv[j + 1];
+            nP[j] = nP[j + 1];
+        }
+        // positions past the segment stay in bounds: interior cells, periodic or
+        // outflow images, or analytic ghosts
+        fetch(k + PF + R, nxt[PF - 1], nv[PF - 1], nP[PF - 1]);
         // epilogue operands of cell k: FP32 issues them before the arithmetic;
         // FP64 loads them after it to keep the register window within 256 VGPRs
         const uint32_t off = cb + (uint32_t)k * sb;

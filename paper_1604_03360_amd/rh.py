@@ -284,7 +284,7 @@ class Hydro:
         u_n, ubar = self._dev(u_n), self._dev(ubar)
         out = self.torch.empty_like(u_n)
         if getattr(self, "_vjp_scratch", None) is None:
-            self._vjp_scratch = self.torch.empty((4,) + tuple(u_n.shape), dtype=self.dtype,
+            self._vjp_scratch = self.torch.empty((3,) + tuple(u_n.shape), dtype=self.dtype,
                                                  device=self.device)
         rh_step_vjp(self.plan, self.t if t is None else t, dt, u_n.data_ptr(), ubar.data_ptr(),
                     out.data_ptr(), self._vjp_scratch.data_ptr())

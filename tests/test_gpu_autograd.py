@@ -62,13 +62,18 @@ def test_adjoint_gradient_against_finite_differences(n, n_steps):
     gmax = np.abs(g64).max()
     for c in cells:
         idx = np.unravel_index(c, e0.shape)
-        # relative step 1e-4 (truncation ~1e-8 relative); the FD itself carries the
-        # rounding noise of two FP64 runs, about eps |loss| / h, added to the bound
+
+        def central(hstep):
+            ep, em = e0.copy(), e0.copy()
+            ep[idx] += hstep
+            em[idx] -= hstep
+            return (loss_fd(rh, spec, ep, n_steps) - loss_fd(rh, spec, em, n_steps)) / (2 * hstep)
+
+        # Richardson-extrapolated central difference (truncation O(h^4)) from steps of
+        # 2e-4 and 1e-4 relative; the rounding noise of the FP64 runs, about
+        # eps |loss| / h per difference, is amplified by (4 + 1/2) / 3 and added to the bound
         hstep = 1e-4 * e0[idx]
-        ep, em = e0.copy(), e0.copy()
-        ep[idx] += hstep
-        em[idx] -= hstep
-        fd = (loss_fd(rh, spec, ep, n_steps) - loss_fd(rh, spec, em, n_steps)) / (2 * hstep)
-        noise = 100 * np.finfo(float).eps * abs(loss64) / hstep
+        fd = (4.0 * central(hstep) - central(2.0 * hstep)) / 3.0
+        noise = 100 * np.finfo(float).eps * abs(loss64) / hstep * 1.5
         assert abs(g64[idx] - fd) <= 1e-6 * gmax + noise + 1e-6 * abs(fd), (idx, g64[idx], fd)
         assert abs(g32[idx] - fd) <= 1e-3 * gmax, (idx, g32[idx], fd)
