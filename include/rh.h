@@ -106,8 +106,7 @@ void rh_plan_destroy(rh_plan* plan);
 size_t rh_state_bytes(const rh_plan* plan);
 
 /* Bytes of the workspace the caller must provide to rh_bind: the two
- * intermediate Runge-Kutta stage states, the L accumulator and the recovered
- * primitives of the current stage (4 state-sized slots). */
+ * intermediate Runge-Kutta stage states and the L accumulator (3 states). */
 size_t rh_workspace_bytes(const rh_plan* plan);
 
 /* Bind caller-owned device buffers and a stream.  state: rh_state_bytes bytes,
@@ -196,6 +195,21 @@ size_t rh_vjp_workspace_bytes(const rh_plan* plan);
 rh_status rh_step_vjp(rh_plan* plan, double t, double dt, const void* u_n, const void* ubar_in,
                       void* ubar_out, void* scratch);
 
+/* One SSP-RK3 step of the bound state, exactly as rh_step with n_steps = 1,
+ * that also leaves its two intermediate stage states u1 (after stage 1) and
+ * u2 (after stage 2) in stages, a caller-owned device buffer of two states
+ * [2][5][nz][ny][nx], for a later rh_step_vjp_stored.  *t_inout advances by dt.
+ * Errors: RH_E_STATE (unbound), RH_E_INVAL (NULL, dt <= 0, aliasing). */
+rh_status rh_step_store(rh_plan* plan, double dt, double* t_inout, void* stages);
+
+/* The adjoint of rh_step_vjp with the stage states supplied instead of
+ * recomputed: stages holds u1, u2 of the step taken from u_n at time t (as
+ * written by rh_step_store), scratch is two states.  Same result as
+ * rh_step_vjp up to rounding order; the bound workspace is overwritten and may
+ * not alias any operand.  Errors: RH_E_STATE (unbound), RH_E_INVAL. */
+rh_status rh_step_vjp_stored(rh_plan* plan, double t, double dt, const void* u_n, const void* stages,
+                             const void* ubar_in, void* ubar_out, void* scratch);
+
 /* ------------------------------------------------------------------------
  * Event-by-event ensembles (batched grids).  The paper's motivation is
  * event-by-event simulation of many independent collisions (abstract and
@@ -218,7 +232,7 @@ void rh_batch_destroy(rh_batch* batch);
  * concatenated buffer; offsets[n_grids] is the total element count. */
 rh_status rh_batch_offsets(const rh_batch* batch, long long* offsets);
 
-/* Bytes of the concatenated state, and of the workspace (4 such buffers). */
+/* Bytes of the concatenated state, and of the workspace (3 such buffers). */
 size_t rh_batch_state_bytes(const rh_batch* batch);
 size_t rh_batch_workspace_bytes(const rh_batch* batch);
 

@@ -4,8 +4,9 @@
 u0 (a device tensor of the plan's dtype and layout [5][nz][ny][nx]) by n_steps
 steps of the library's SSP-RK3 scheme and returns the final state.  The forward
 pass keeps a checkpoint of the state every ``every`` steps; the backward pass
-replays each checkpointed segment forward to recover the per-step states and
-then applies the hand-written adjoint of one step (``rh_step_vjp``) in reverse.
+replays each checkpointed segment forward, keeping every step's input and its
+two Runge-Kutta stage states (``rh_step_store``), and then applies the
+hand-written adjoint of one step (``rh_step_vjp_stored``) in reverse.
 All arithmetic runs in the library's kernels; this module only sequences calls
 and keeps the checkpoints.
 """
@@ -43,14 +44,15 @@ class HydroRun(torch.autograd.Function):
         for seg in reversed(range(len(ctx.checkpoints))):
             u_c, t_c = ctx.checkpoints[seg]
             steps = min(every, ctx.n_steps - seg * every)
-            states = [u_c]
+            states, stages = [], []
             hydro.state.copy_(u_c)
             hydro.t = t_c
-            for _ in range(steps - 1):
-                hydro.step(dt, 1)
+            for _ in range(steps):
                 states.append(hydro.state.clone())
+                stages.append(hydro.step_store(dt))
             for j in reversed(range(steps)):
-                ubar = hydro.step_vjp(states[j], ubar, dt, t=t_c + j * dt)
+                ubar = hydro.step_vjp_stored(states[j], stages[j], ubar, dt, t=t_c + j * dt)
+            del states, stages
         hydro.t = t_end
         return ubar, None, None, None, None
 

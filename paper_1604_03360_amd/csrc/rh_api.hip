@@ -122,7 +122,6 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
     a.dt = (T)dt;
     a.stage = stage;
     a.hb.t = t;
-    a.prims = (T*)p->ws + 3 * 5 * (size_t)p->ncell;   // the workspace's primitive slot
     const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
     const double h[3] = {p->d.dx, p->d.dy, p->d.dz};
     int active[3], na = 0;
@@ -140,7 +139,6 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
         const int d = active[i];
         rh::SweepArgs<T> b = a;
         b.first = i == 0;
-        b.prim_mode = i == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
         b.stage = i == na - 1 ? stage : rh::STAGE_WRITE_L;
         b.bc = p->d.bc[d];
         b.inv_h = (T)(1.0 / h[d]);
@@ -153,12 +151,12 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
 }
 
 template <class T>
-rh_status step_impl(rh_plan* p, double dt, int nsteps, double t) {
+rh_status step_impl(rh_plan* p, double dt, int nsteps, double t, T* stages = nullptr) {
     const size_t S = 5 * (size_t)p->ncell;
     T* U0 = (T*)p->state;
-    T* U1 = (T*)p->ws;
+    T* U1 = stages ? stages : (T*)p->ws;   // stage states go to the caller's store if given
     T* U2 = U1 + S;
-    T* Lc = U2 + S;
+    T* Lc = (T*)p->ws + 2 * S;
     for (int s = 0; s < nsteps; ++s) {
         rh_status st;
         st = evaluate<T>(p, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
@@ -247,7 +245,7 @@ void rh_plan_destroy(rh_plan* p) {
 
 size_t rh_state_bytes(const rh_plan* p) { return p ? 5 * (size_t)p->ncell * p->elem : 0; }
 
-size_t rh_workspace_bytes(const rh_plan* p) { return p ? 4 * rh_state_bytes(p) : 0; }
+size_t rh_workspace_bytes(const rh_plan* p) { return p ? 3 * rh_state_bytes(p) : 0; }
 
 rh_status rh_bind(rh_plan* p, void* state, void* workspace, void* stream) {
     if (!p) return fail(RH_E_INVAL, "plan is NULL");
@@ -293,7 +291,7 @@ rh_status rh_apply_L(rh_plan* p, double t, void* L_out) {
     const char* lo = (const char*)L_out;
     const char* s0 = (const char*)p->state;
     const char* w0 = (const char*)p->ws;
-    if ((lo < s0 + sb && s0 < lo + sb) || (lo < w0 + 4 * sb && w0 < lo + sb))
+    if ((lo < s0 + sb && s0 < lo + sb) || (lo < w0 + 3 * sb && w0 < lo + sb))
         return fail(RH_E_INVAL, "L_out aliases the bound buffers");
     if (is_fp32(p))
         return evaluate<float>(p, (const float*)p->state, (const float*)p->state, (float*)L_out,
@@ -516,11 +514,9 @@ rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T
     B.base.hb.e0 = b->d[0].hubble_e0;
     B.base.hb.n0 = b->d[0].hubble_n0;
     B.base.clamps = b->d_clamps;
-    B.base.prims = (T*)b->ws + 3 * (size_t)b->off[b->ngrid];
     for (int d = 0; d < 3; ++d) {
         rh::BatchArgs<T> Bd = B;
         Bd.base.first = d == 0;
-        Bd.base.prim_mode = d == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
         Bd.base.stage = d == 2 ? stage : rh::STAGE_WRITE_L;
         rh_status st = batch_timed(b, s, RH_KERNEL_SWEEP_X + d, [&] {
             return rh::launch_sweep_batch<T>(d, b->scheme, b->tile_x, Bd, b->nblocks[d], s);
@@ -683,7 +679,7 @@ rh_status rh_batch_offsets(const rh_batch* b, long long* offsets) {
 
 size_t rh_batch_state_bytes(const rh_batch* b) { return b ? (size_t)b->off[b->ngrid] * b->elem : 0; }
 
-size_t rh_batch_workspace_bytes(const rh_batch* b) { return b ? 4 * rh_batch_state_bytes(b) : 0; }
+size_t rh_batch_workspace_bytes(const rh_batch* b) { return b ? 3 * rh_batch_state_bytes(b) : 0; }
 
 rh_status rh_batch_bind(rh_batch* b, void* state, void* workspace, void* stream) {
     if (!b) return fail(RH_E_INVAL, "batch is NULL");
@@ -834,8 +830,6 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
                 B.base.clamps = b->d_clamps;
                 B.base.first = 1;
                 B.base.stage = rh::STAGE_WRITE_L;
-                B.base.prims = (float*)b->ws + 3 * S;
-                B.base.prim_mode = cls == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
                 hipError_t er = rh::launch_sweep_batch<float>(cls, b->scheme, b->tile_x, B, b->nblocks[cls], b->stream);
                 return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
             }
@@ -851,8 +845,6 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
             B.base.clamps = b->d_clamps;
             B.base.first = 1;
             B.base.stage = rh::STAGE_WRITE_L;
-            B.base.prims = (double*)b->ws + 3 * S;
-            B.base.prim_mode = cls == 0 ? rh::PRIMS_STORE : rh::PRIMS_LOAD;
             hipError_t er = rh::launch_sweep_batch<double>(cls, b->scheme, b->tile_x, B, b->nblocks[cls], b->stream);
             return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
         };
@@ -880,10 +872,6 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
         }
     }
     b->tile_x = best_tx;
-    if (rs == RH_OK && (rs = upload_table(b)) == RH_OK) {
-        float ms;
-        rs = time_class(0, &ms);   // fills the primitive slot the y and z timings load
-    }
     for (int d = 1; d < 3 && rs == RH_OK; ++d) {
         best_ms = 1e30f;
         for (int sg : {16, 32, 48, 64, 128}) {
@@ -1034,22 +1022,17 @@ rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, T a, co
     return RH_OK;
 }
 
+// Adjoint of one step given its stage states u1, u2 (b2, b1: scratch states)
 template <class T>
-rh_status step_vjp_impl(rh_plan* p, double t, double dt, const T* un, const T* bin, T* bout, T* scratch) {
+rh_status step_vjp_core(rh_plan* p, double t, double dt, const T* un, const T* u1, const T* u2, const T* bin,
+                        T* bout, T* b2, T* b1) {
     const size_t S = 5 * (size_t)p->ncell;
-    T* u1 = scratch;
-    T* u2 = scratch + S;
-    T* b2 = scratch + 2 * S;
-    T* Lc = (T*)p->ws + 2 * S;   // the bound workspace's L accumulator
-    rh_status st = evaluate<T>(p, un, un, Lc, u1, t, dt, rh::STAGE_1);
-    if (st == RH_OK) st = evaluate<T>(p, u1, un, Lc, u2, t + dt, dt, rh::STAGE_2);
-    if (st != RH_OK) return st;
     const T td = (T)dt;
+    rh_status st;
     // b2 = 2/3 b + 2/3 dt J(u2)^T b
     if ((st = vjp_impl<T>(p, t + 0.5 * dt, u2, bin, b2, (T)(2.0 / 3.0), bin, (T)(2.0 / 3.0) * td)) != RH_OK)
         return st;
-    // b1 = 1/4 b2 + 1/4 dt J(u1)^T b2   (b1 stored in u2's slot, u2 no longer needed)
-    T* b1 = u2;
+    // b1 = 1/4 b2 + 1/4 dt J(u1)^T b2
     if ((st = vjp_impl<T>(p, t + dt, u1, b2, b1, (T)0.25, b2, (T)0.25 * td)) != RH_OK) return st;
     // out = (1/3 b + 3/4 b2 + b1) + dt J(un)^T b1
     st = timed_launch(p, RH_KERNEL_OTHER, [&] {
@@ -1058,6 +1041,20 @@ rh_status step_vjp_impl(rh_plan* p, double t, double dt, const T* un, const T* b
     }, "combine launch");
     if (st != RH_OK) return st;
     return vjp_impl<T>(p, t, un, b1, bout, (T)1, bout, td);
+}
+
+// The stage states are recomputed into scratch[0..1]; b2 goes to scratch[2]
+// and b1 reuses u2's slot once J(u2) has been applied.
+template <class T>
+rh_status step_vjp_impl(rh_plan* p, double t, double dt, const T* un, const T* bin, T* bout, T* scratch) {
+    const size_t S = 5 * (size_t)p->ncell;
+    T* u1 = scratch;
+    T* u2 = scratch + S;
+    T* Lc = (T*)p->ws + 2 * S;   // the bound workspace's L accumulator
+    rh_status st = evaluate<T>(p, un, un, Lc, u1, t, dt, rh::STAGE_1);
+    if (st == RH_OK) st = evaluate<T>(p, u1, un, Lc, u2, t + dt, dt, rh::STAGE_2);
+    if (st != RH_OK) return st;
+    return step_vjp_core<T>(p, t, dt, un, u1, u2, bin, bout, scratch + 2 * S, u2);
 }
 
 // [a, a + na) and [b, b + nb) intersect
@@ -1077,11 +1074,54 @@ rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void*
     if (!u || !w || !out) return fail(RH_E_INVAL, "NULL buffer");
     const size_t sb = rh_state_bytes(p);
     if (overlaps(out, sb, u, sb) || overlaps(out, sb, w, sb)) return fail(RH_E_INVAL, "out aliases u or w");
-    if (overlaps(p->ws, 4 * sb, u, sb) || overlaps(p->ws, 4 * sb, w, sb) || overlaps(p->ws, 4 * sb, out, sb))
+    if (overlaps(p->ws, 3 * sb, u, sb) || overlaps(p->ws, 3 * sb, w, sb) || overlaps(p->ws, 3 * sb, out, sb))
         return fail(RH_E_INVAL, "an operand aliases the bound workspace");
     return is_fp32(p) ? vjp_impl<float>(p, t, (const float*)u, (const float*)w, (float*)out, 0.0f, nullptr, 1.0f)
                       : vjp_impl<double>(p, t, (const double*)u, (const double*)w, (double*)out, 0.0, nullptr,
                                          1.0);
+}
+
+rh_status rh_step_store(rh_plan* p, double dt, double* t_inout, void* stages) {
+    rh_status st = check_bound(p);
+    if (st != RH_OK) return st;
+    if (!t_inout || !stages) return fail(RH_E_INVAL, "NULL argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
+    const size_t sb = rh_state_bytes(p);
+    if (overlaps(stages, 2 * sb, p->state, sb) || overlaps(stages, 2 * sb, p->ws, 3 * sb))
+        return fail(RH_E_INVAL, "stages alias the bound state or workspace");
+    st = is_fp32(p) ? step_impl<float>(p, dt, 1, *t_inout, (float*)stages)
+                    : step_impl<double>(p, dt, 1, *t_inout, (double*)stages);
+    if (st == RH_OK) *t_inout += dt;
+    return st;
+}
+
+rh_status rh_step_vjp_stored(rh_plan* p, double t, double dt, const void* u_n, const void* stages,
+                             const void* ubar_in, void* ubar_out, void* scratch) {
+    rh_status st = check_bound(p);
+    if (st != RH_OK) return st;
+    if (!u_n || !stages || !ubar_in || !ubar_out || !scratch) return fail(RH_E_INVAL, "NULL buffer");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
+    const size_t sb = rh_state_bytes(p);
+    if (overlaps(scratch, 2 * sb, u_n, sb) || overlaps(scratch, 2 * sb, stages, 2 * sb) ||
+        overlaps(scratch, 2 * sb, ubar_in, sb) || overlaps(scratch, 2 * sb, ubar_out, sb))
+        return fail(RH_E_INVAL, "scratch aliases an operand");
+    if (overlaps(ubar_out, sb, u_n, sb) || overlaps(ubar_out, sb, stages, 2 * sb))
+        return fail(RH_E_INVAL, "ubar_out aliases u_n or the stages");
+    const char* ws = (const char*)p->ws;
+    if (overlaps(ws, 3 * sb, u_n, sb) || overlaps(ws, 3 * sb, stages, 2 * sb) || overlaps(ws, 3 * sb, ubar_in, sb) ||
+        overlaps(ws, 3 * sb, ubar_out, sb) || overlaps(ws, 3 * sb, scratch, 2 * sb))
+        return fail(RH_E_INVAL, "an operand aliases the bound workspace");
+    const size_t S = 5 * (size_t)p->ncell;
+    if (is_fp32(p)) {
+        const float* u1 = (const float*)stages;
+        float* sc = (float*)scratch;
+        return step_vjp_core<float>(p, t, dt, (const float*)u_n, u1, u1 + S, (const float*)ubar_in,
+                                    (float*)ubar_out, sc, sc + S);
+    }
+    const double* u1 = (const double*)stages;
+    double* sc = (double*)scratch;
+    return step_vjp_core<double>(p, t, dt, (const double*)u_n, u1, u1 + S, (const double*)ubar_in,
+                                 (double*)ubar_out, sc, sc + S);
 }
 
 size_t rh_vjp_workspace_bytes(const rh_plan* p) { return p ? 3 * rh_state_bytes(p) : 0; }
@@ -1098,8 +1138,8 @@ rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const vo
         return fail(RH_E_INVAL, "scratch aliases an operand");
     if (overlaps(ubar_out, sb, u_n, sb)) return fail(RH_E_INVAL, "ubar_out aliases u_n");
     const char* ws = (const char*)p->ws;
-    if (overlaps(ws, 4 * sb, u_n, sb) || overlaps(ws, 4 * sb, ubar_in, sb) ||
-        overlaps(ws, 4 * sb, ubar_out, sb) || overlaps(ws, 4 * sb, scratch, 3 * sb))
+    if (overlaps(ws, 3 * sb, u_n, sb) || overlaps(ws, 3 * sb, ubar_in, sb) ||
+        overlaps(ws, 3 * sb, ubar_out, sb) || overlaps(ws, 3 * sb, scratch, 3 * sb))
         return fail(RH_E_INVAL, "an operand aliases the bound workspace");
     return is_fp32(p) ? step_vjp_impl<float>(p, t, dt, (const float*)u_n, (const float*)ubar_in,
                                              (float*)ubar_out, (float*)scratch)

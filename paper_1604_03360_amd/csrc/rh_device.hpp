@@ -85,38 +85,6 @@ __device__ __forceinline__ void recover_vp(double E, double Mx, double My, doubl
     p = (E2 - M2) * a * r;
 }
 
-// The same recovery for all three velocity components (each v_i is computed by
-// the same expression as recover_vp<i>, so the values agree bit for bit).
-__device__ __forceinline__ void recover_all(double E, double Mx, double My, double Mz, double v[3],
-                                            double& p, unsigned& clamped) {
-    double M[3] = {Mx, My, Mz};
-    if (E < kEFloor) {
-        v[0] = v[1] = v[2] = 0.0;
-        p = (E > 0.0 ? E : 0.0) / 3.0;
-        ++clamped;
-        return;
-    }
-    double M2 = Mx * Mx + My * My + Mz * Mz;
-    const double E2 = E * E;
-    const double cap = (1.0 - kVDelta) * E * E;
-    if (M2 > cap) {
-        const double s = sqrt(cap / M2);
-        M[0] *= s;
-        M[1] *= s;
-        M[2] *= s;
-        M2 = cap;
-        ++clamped;
-    }
-    const double D = sqrt(4.0 * E2 - 3.0 * M2);
-    const double a = 2.0 * E + D;
-    const double b = E + D;
-    const double r = fast_rcp(a * b);
-    v[0] = 3.0 * b * r * M[0];
-    v[1] = 3.0 * b * r * M[1];
-    v[2] = 3.0 * b * r * M[2];
-    p = (E2 - M2) * a * r;
-}
-
 // Split fluxes f+- = (F_d(u) +- u) / 2 of one cell along axis DIR, given the
 // velocity along DIR and the pressure.
 template <class T, int DIR>

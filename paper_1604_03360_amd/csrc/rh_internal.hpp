@@ -29,11 +29,7 @@ struct SweepArgs {
     T eps;              // WENO epsilon
     HubbleBC hb;        // analytic boundary data (bc == HUBBLE)
     unsigned* clamps;   // floor counter
-    T* prims;           // recovered (vx, vy, vz, p) per cell, fields 0..3 of a state-sized buffer
-    int prim_mode;      // PRIMS_*: recover here, recover and store (first sweep), or load
 };
-
-enum { PRIMS_RECOVER = 0, PRIMS_STORE = 1, PRIMS_LOAD = 2 };
 
 // One grid of a batched (event-ensemble) launch.  All of the grid's fields live
 // at element offset `off` of every batched buffer, in the single-grid layout.

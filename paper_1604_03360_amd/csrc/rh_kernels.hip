@@ -55,56 +55,6 @@ __device__ __forceinline__ void load_cell(const SweepArgs<T>& A, int ix, int iy,
 // One reconstruction from a window of 2R split fluxes of cells i-R+1 .. i+R
 // (interface i+1/2): plus = left-biased on f+, minus = mirrored on f-.
 // WENO5 takes 4 eps (its smoothness indicators are carried as 4 beta).
-// State of a cell with the velocity along DIR and the pressure.  The first sweep
-// of an evaluation of L recovers them (FP64) and, for the cells it owns, stores
-// all three velocity components and p; later sweeps load them.  Ghost cells map
-// to interior cells (periodic, outflow) or are analytic (recovered on the spot).
-template <class T, int DIR>
-__device__ __forceinline__ void cell_state_vp(const SweepArgs<T>& A, int ix, int iy, int iz, bool own,
-                                              T u[5], T& v, T& P, unsigned& clamped) {
-    int c[3] = {ix, iy, iz};
-    const int nd = A.n[DIR];
-    int m = c[DIR];
-    if (m < 0 || m >= nd) {
-        if (A.bc == RH_BC_PERIODIC) {
-            m %= nd;
-            if (m < 0) m += nd;
-            c[DIR] = m;
-        } else if (A.bc == RH_BC_OUTFLOW) {
-            c[DIR] = m < 0 ? 0 : nd - 1;
-        } else {
-            load_cell<T, DIR>(A, ix, iy, iz, u);
-            double vd, p;
-            recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, p, clamped);
-            v = (T)vd;
-            P = (T)p;
-            return;
-        }
-    }
-    const long long id = c[0] + (long long)A.n[0] * (c[1] + (long long)A.n[1] * c[2]);
-#pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
-    if (A.prim_mode == PRIMS_LOAD) {
-        v = A.prims[DIR * A.fstride + id];
-        P = A.prims[3 * A.fstride + id];
-    } else if (A.prim_mode == PRIMS_STORE) {
-        double vv[3], p;
-        recover_all((double)u[0], (double)u[1], (double)u[2], (double)u[3], vv, p, clamped);
-        if (own) {
-#pragma unroll
-            for (int f = 0; f < 3; ++f) A.prims[f * A.fstride + id] = (T)vv[f];
-            A.prims[3 * A.fstride + id] = (T)p;
-        }
-        v = (T)vv[DIR];
-        P = (T)p;
-    } else {
-        double vd, p;
-        recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, p, clamped);
-        v = (T)vd;
-        P = (T)p;
-    }
-}
-
 template <class T, int ORDER>
 __device__ __forceinline__ T recon_plus(const T* w, T eps) {
     if constexpr (ORDER == 5) return weno5<T>(w[0], w[1], w[2], w[3], w[4], (T)4 * eps);
@@ -161,10 +111,9 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
         const int ly = idx / PW, lx = idx - ly * PW;
         const int row = r0 + ly, gx = x0 + lx - G;
         if (row < nrows && gx < nx + G) {
-            T u[5], fp[5], fm[5], v, P;
-            const bool own = lx >= G && lx < G + TX && gx < nx;
-            cell_state_vp<T, 0>(A, gx, row % ny, row / ny, own, u, v, P, clamped);
-            split_flux_vp<T, 0>(u, v, P, fp, fm);
+            T u[5], fp[5], fm[5];
+            load_cell<T, 0>(A, gx, row % ny, row / ny, u);
+            split_flux<T, 0>(u, fp, fm, clamped);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 sp[(c * TY + ly) * PW + lx] = fp[c];
@@ -232,11 +181,6 @@ __device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
     *(T*)((char*)base + off) = v;
 }
 
-// Cells each rolling lane keeps in flight ahead of the one it computes.
-#ifndef RH_ROLL_PREFETCH
-#define RH_ROLL_PREFETCH 1
-#endif
-
 // bx: 256-lane chunk of the (x, w) plane; by: segment along the sweep axis
 template <class T, int ORDER, int DIR>
 __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned bx, int by) {
@@ -258,18 +202,15 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
     const long long F = A.fstride;
     unsigned clamped = 0;
 
-    // state, normal velocity and pressure of line cell m
-    auto fetch = [&](int m, T u[5], T& v, T& P) {
-        if (m >= 0 && m < nd && A.prim_mode == PRIMS_LOAD) {
+    auto fetch = [&](int m, T u[5]) {
+        if (m >= 0 && m < nd) {
             const uint32_t off = cb + (uint32_t)m * sb;
 #pragma unroll
             for (int f = 0; f < 5; ++f) u[f] = ld_off(A.us + f * F, off);
-            v = ld_off(A.prims + DIR * F, off);
-            P = ld_off(A.prims + 3 * F, off);
         } else if (DIR == 1) {
-            cell_state_vp<T, DIR>(A, x, m, w, m >= k0 && m < kend, u, v, P, clamped);
+            load_cell<T, DIR>(A, x, m, w, u);
         } else {
-            cell_state_vp<T, DIR>(A, x, w, m, m >= k0 && m < kend, u, v, P, clamped);
+            load_cell<T, DIR>(A, x, w, m, u);
         }
     };
 
@@ -277,9 +218,9 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
     T wp[5][W], wm[5][W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        T u[5], fp[5], fm[5], v, P;
-        fetch(k0 - R + j, u, v, P);
-        split_flux_vp<T, DIR>(u, v, P, fp, fm);
+        T u[5], fp[5], fm[5];
+        fetch(k0 - R + j, u);
+        split_flux<T, DIR>(u, fp, fm, clamped);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             wp[c][j] = fp[c];
@@ -291,26 +232,13 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
     for (int c = 0; c < 5; ++c)
         Fl[c] = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
 
-    // cells k+R .. k+R+PF-1 are in flight while iteration k computes
-    constexpr int PF = RH_ROLL_PREFETCH;
-    T nxt[PF][5], nv[PF], nP[PF];
-#pragma unroll
-    for (int j = 0; j < PF; ++j) fetch(k0 + R + j, nxt[j], nv[j], nP[j]);
+    T nxt[5];
+    fetch(k0 + R, nxt);
     for (int k = k0; k < kend; ++k) {
         T u[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) u[f] = nxt[0][f];
-        const T v = nv[0], P = nP[0];
-#pragma unroll
-        for (int j = 0; j + 1 < PF; ++j) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) nxt[j][f] = nxt[j + 1][f];
-            nv[j] = nv[j + 1];
-            nP[j] = nP[j + 1];
-        }
-        // positions past the segment stay in bounds: interior cells, periodic or
-        // outflow images, or analytic ghosts
-        fetch(k + PF + R, nxt[PF - 1], nv[PF - 1], nP[PF - 1]);
+        for (int f = 0; f < 5; ++f) u[f] = nxt[f];
+        fetch(k + 1 + R, nxt);   // next iteration's new cell, in flight during this one
         // epilogue operands of cell k: FP32 issues them before the arithmetic;
         // FP64 loads them after it to keep the register window within 256 VGPRs
         const uint32_t off = cb + (uint32_t)k * sb;
@@ -325,7 +253,7 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
         };
         if constexpr (sizeof(T) == 4) load_epilogue();
         T fp[5], fm[5];
-        split_flux_vp<T, DIR>(u, v, P, fp, fm);
+        split_flux<T, DIR>(u, fp, fm, clamped);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
 #pragma unroll
@@ -418,7 +346,6 @@ __device__ __forceinline__ SweepArgs<T> grid_args(const BatchArgs<T>& B, int g, 
     A.u0 = B.base.u0 + G.off;
     A.lacc = B.base.lacc + G.off;
     A.uout = B.base.uout ? B.base.uout + G.off : nullptr;
-    A.prims = B.base.prims ? B.base.prims + G.off : nullptr;
     A.fstride = (long long)G.n[0] * G.n[1] * G.n[2];
     A.n[0] = G.n[0];
     A.n[1] = G.n[1];

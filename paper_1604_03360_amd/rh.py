@@ -74,6 +74,8 @@ def library():
         L.rh_vjp_workspace_bytes.argtypes = [vp]
         L.rh_vjp_workspace_bytes.restype = ctypes.c_size_t
         L.rh_step_vjp.argtypes = [vp, d, d, vp, vp, vp, vp]
+        L.rh_step_store.argtypes = [vp, d, ctypes.POINTER(d), vp]
+        L.rh_step_vjp_stored.argtypes = [vp, d, d, vp, vp, vp, vp, vp]
         llp = ctypes.POINTER(ctypes.c_longlong)
         ip = ctypes.POINTER(ctypes.c_int)
         L.rh_batch_create.argtypes = [pp, i, ctypes.POINTER(rh_grid_desc)]
@@ -191,6 +193,18 @@ def rh_step_vjp(plan, t, dt, un_ptr, bin_ptr, bout_ptr, scratch_ptr):
                                  ctypes.c_void_p(scratch_ptr)))
 
 
+def rh_step_store(plan, dt, t, stages_ptr):
+    tt = ctypes.c_double(t)
+    _check(library().rh_step_store(plan, float(dt), ctypes.byref(tt), ctypes.c_void_p(stages_ptr)))
+    return tt.value
+
+
+def rh_step_vjp_stored(plan, t, dt, un_ptr, stages_ptr, bin_ptr, bout_ptr, scratch_ptr):
+    _check(library().rh_step_vjp_stored(plan, float(t), float(dt), ctypes.c_void_p(un_ptr),
+                                        ctypes.c_void_p(stages_ptr), ctypes.c_void_p(bin_ptr),
+                                        ctypes.c_void_p(bout_ptr), ctypes.c_void_p(scratch_ptr)))
+
+
 def make_desc(shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC,) * 3,
               eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False):
     d = rh_grid_desc()
@@ -222,7 +236,7 @@ class Hydro:
         nx, ny, nz = self.shape
         self.device = torch.device(device)
         self.state = torch.zeros((5, nz, ny, nx), dtype=self.dtype, device=self.device)
-        self.workspace = torch.zeros((4, 5, nz, ny, nx), dtype=self.dtype, device=self.device)
+        self.workspace = torch.zeros((3, 5, nz, ny, nx), dtype=self.dtype, device=self.device)
         assert self.state.numel() * self.state.element_size() == rh_state_bytes(self.plan)
         assert self.workspace.numel() * self.workspace.element_size() == rh_workspace_bytes(self.plan)
         self.t = float(t)
@@ -288,6 +302,24 @@ class Hydro:
                                                  device=self.device)
         rh_step_vjp(self.plan, self.t if t is None else t, dt, u_n.data_ptr(), ubar.data_ptr(),
                     out.data_ptr(), self._vjp_scratch.data_ptr())
+        return out
+
+    def step_store(self, dt, stages=None):
+        """One step that also returns its two stage states ([2][5][nz][ny][nx])."""
+        if stages is None:
+            stages = self.torch.empty((2,) + tuple(self.state.shape), dtype=self.dtype, device=self.device)
+        self.t = rh_step_store(self.plan, dt, self.t, stages.data_ptr())
+        return stages
+
+    def step_vjp_stored(self, u_n, stages, ubar, dt, t=None):
+        """Adjoint of one SSP-RK3 step from u_n whose stage states are given."""
+        u_n, ubar = self._dev(u_n), self._dev(ubar)
+        out = self.torch.empty_like(u_n)
+        if getattr(self, "_vjp_scratch", None) is None:
+            self._vjp_scratch = self.torch.empty((3,) + tuple(u_n.shape), dtype=self.dtype,
+                                                 device=self.device)
+        rh_step_vjp_stored(self.plan, self.t if t is None else t, dt, u_n.data_ptr(), stages.data_ptr(),
+                           ubar.data_ptr(), out.data_ptr(), self._vjp_scratch.data_ptr())
         return out
 
     def close(self):
@@ -405,7 +437,7 @@ class Batch:
         self.dtype = torch.float32 if precision == RH_PREC_FP32 else torch.float64
         total = self.offsets[-1]
         self.state = torch.zeros(total, dtype=self.dtype, device=self.device)
-        self.workspace = torch.zeros(4 * total, dtype=self.dtype, device=self.device)
+        self.workspace = torch.zeros(3 * total, dtype=self.dtype, device=self.device)
         self.t = float(specs[0].get("t0", 0.0))
         rh_batch_bind(self.batch, self.state.data_ptr(), self.workspace.data_ptr(),
                       torch.cuda.current_stream(self.device).cuda_stream)

@@ -104,3 +104,64 @@ def test_charge_adjoint_is_zero_for_energy_momentum_weights():
     got = h.vjp(u, w).cpu().numpy()
     h.close()
     assert np.all(got[4] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["smooth_outflow", "hubble", "hotspots"])
+def test_stored_stages_give_the_recomputed_adjoint(case, precision):
+    """rh_step_store advances the state exactly as rh_step and records the two
+    stage states, which equal the oracle's (FP64); the adjoint from the stored
+    stages equals the recomputing adjoint bitwise (same kernels, same inputs)."""
+    rh = rh_module()
+    import torch
+    prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
+    spec = CASES[case](5)
+    dt, t0 = spec["dt"], spec["t0"]
+    h, u, w = _setup(rh, spec, prec)
+    h.set_primitive(spec["prim"])
+    u_n = h.state.clone()
+    stages = h.step_store(dt)
+    after_store = h.state.clone()
+    assert h.t == pytest.approx(t0 + dt, abs=1e-12)
+    h.state.copy_(u_n)
+    h.t = t0
+    h.step(dt, 1)
+    assert torch.equal(h.state, after_store)
+    wd = torch.tensor(w, dtype=h.dtype, device="cuda")
+    a = h.step_vjp(u_n, wd, dt, t=t0)
+    b = h.step_vjp_stored(u_n, stages, wd, dt, t=t0)
+    assert torch.equal(a, b)
+    if precision == "fp64":
+        g = oracle.grid_from_spec(spec)
+        un = u_n.cpu().numpy()
+        u1 = un + dt * oracle.apply_L(g, un, t0)
+        u2 = 0.75 * un + 0.25 * (u1 + dt * oracle.apply_L(g, u1, t0 + dt))
+        st = stages.cpu().numpy()
+        for got, ref in ((st[0], u1), (st[1], u2)):
+            err = np.abs(got - ref).reshape(5, -1).max(axis=1) / np.abs(ref).max()
+            assert np.all(err <= 1e-12), err
+    h.close()
+
+
+def test_stored_adjoint_rejects_aliasing():
+    rh = rh_module()
+    import torch
+    spec = CASES["tiny_periodic"](5)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP64)
+    stages = h.step_store(spec["dt"])
+    u_n = h.state.clone()
+    ubar = torch.ones_like(u_n)
+    # scratch overlapping the stages, and an output overlapping the stages
+    with pytest.raises(rh.RHError) as e:
+        rh.rh_step_vjp_stored(h.plan, 0.0, spec["dt"], u_n.data_ptr(), stages.data_ptr(), ubar.data_ptr(),
+                              torch.empty_like(u_n).data_ptr(), stages.data_ptr())
+    assert e.value.status == rh.RH_E_INVAL
+    with pytest.raises(rh.RHError) as e:
+        rh.rh_step_vjp_stored(h.plan, 0.0, spec["dt"], u_n.data_ptr(), stages.data_ptr(), ubar.data_ptr(),
+                              stages[1].data_ptr(), torch.empty((2,) + tuple(u_n.shape), dtype=u_n.dtype,
+                                                                device="cuda").data_ptr())
+    assert e.value.status == rh.RH_E_INVAL
+    with pytest.raises(rh.RHError) as e:
+        rh.rh_step_store(h.plan, spec["dt"], 0.0, h.workspace.data_ptr())
+    assert e.value.status == rh.RH_E_INVAL
+    h.close()
