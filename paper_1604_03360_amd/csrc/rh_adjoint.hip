@@ -88,6 +88,44 @@ __device__ __forceinline__ void adj_load(const AdjArgs<T>& A, const Column<T, DI
     for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
 }
 
+// State at line position m with its velocity along the sweep axis and pressure:
+// from the recovery pack when one is given (interior, periodic and outflow
+// positions), else recovered here in FP64 (always for analytic ghosts).
+template <class T, int DIR, bool PACK>
+__device__ __forceinline__ void adj_state(const AdjArgs<T>& A, const Column<T, DIR>& C, int m, T u[5], T& v,
+                                          T& P) {
+    const int nd = A.n[DIR];
+    int mm = m;
+    bool analytic = false;
+    if (m < 0 || m >= nd) {
+        if (A.bc == RH_BC_PERIODIC) {
+            mm = m % nd;
+            if (mm < 0) mm += nd;
+        } else if (A.bc == RH_BC_OUTFLOW) {
+            mm = m < 0 ? 0 : nd - 1;
+        } else {
+            analytic = true;
+        }
+    }
+    if (analytic) {
+        adj_load<T, DIR>(A, C, m, u);
+    } else {
+        const long long id = C.base + mm * C.stride;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
+        if constexpr (PACK) {
+            v = A.pk[id] * u[1 + DIR];
+            P = A.pk[A.fstride + id];
+            return;
+        }
+    }
+    double vd, pd;
+    unsigned dummy = 0;
+    recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, pd, dummy);
+    v = (T)vd;
+    P = (T)pd;
+}
+
 // weights at line position m: zero outside the grid unless periodic
 template <class T, int DIR>
 __device__ __forceinline__ void adj_weight(const AdjArgs<T>& A, const Column<T, DIR>& C, int m, T w[5]) {
@@ -129,7 +167,7 @@ struct AdjGroup {
     static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? RH_ADJ_GROUP_F32_W5 : RH_ADJ_GROUP_OTHER;
 };
 
-template <class T, int ORDER, int DIR, int CLO, int CHI>
+template <class T, int ORDER, int DIR, bool PACK, int CLO, int CHI>
 __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R, NC = CHI - CLO;
     const int nd = A.n[DIR];
@@ -144,13 +182,9 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     const int own_hi = (!periodic && k1 == nd && A.bc == RH_BC_OUTFLOW) ? (1 << 30) : k1;
     const T eps = A.eps;
     const T half = (T)0.5;
-    unsigned dummy = 0;
 
     // split fluxes of the group's components from a cell state
-    auto group_flux = [&](const T u[5], T fp[NC], T fm[NC]) {
-        double vd = 0.0, pd = 0.0;
-        if constexpr (CHI > 1) recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, pd, dummy);
-        const T v = (T)vd, P = (T)pd;
+    auto group_flux = [&](const T u[5], T v, T P, T fp[NC], T fm[NC]) {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const int c = CLO + q;
@@ -176,17 +210,65 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     // state and running adjoint of the cell updated next; consecutive updates
     // of one cell (outflow edges) continue from registers
     int last_tgt = -1;
-    T ubo[5], uf[5];
+    T ubo[5], uf[5], pkf[5];
     auto fetch_cell = [&](int tgt) {
         const long long id = C.base + (long long)tgt * C.stride;
 #pragma unroll
         for (int f = 0; f < 5; ++f) uf[f] = A.u[f * A.fstride + id];
+        if constexpr (PACK && CHI > 1) {
+            pkf[0] = A.pk[id];
+#pragma unroll
+            for (int q = 1; q < 5; ++q) pkf[q] = A.pk[(q + 1) * A.fstride + id];
+        }
         if (tgt == last_tgt) return;
+        if (CLO == 0 && A.zero_init) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) ubo[f] = (T)0;
+            return;
+        }
 #pragma unroll
         for (int f = 0; f < 5; ++f) ubo[f] = A.ub[f * A.fstride + id];
     };
     // ub += scale * sum over the group of (d f+_c/du)^T a+_c + (d f-_c/du)^T a-_c
+    auto finish_pack = [&](int tgt, const T apj[NC], const T amj[NC]) {
+        // pkf = (kappa, dkappa/dE, dkappa/dM2, dP/dE, dP/dM2); v_d = kappa M_d
+        T lam[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, g[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            lam[CLO + q] = half * (apj[q] + amj[q]);
+            g[CLO + q] = half * (apj[q] - amj[q]);
+        }
+        g[1 + DIR] += lam[0];
+        if constexpr (CHI > 1) {
+            const T Md = uf[1 + DIR], vd = pkf[0] * Md;
+            T S = (T)0;
+#pragma unroll
+            for (int c = (CLO > 1 ? CLO : 1); c < CHI; ++c) {
+                S += lam[c] * uf[c];
+                g[c] += lam[c] * vd;
+            }
+            const T lp = lam[1 + DIR];
+            // dv_d/dE = M_d kappa_E, dv_d/dM_m = kappa delta_dm + 2 M_d M_m kappa_M2,
+            // dP/dE = P_E, dP/dM_m = 2 M_m P_M2
+            g[0] += S * (Md * pkf[1]) + lp * pkf[3];
+            const T sk = (T)2 * S * Md * pkf[2], sp = (T)2 * lp * pkf[4];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) g[1 + m] += (sk + sp) * uf[1 + m];
+            g[1 + DIR] += S * pkf[0];
+        }
+        const long long id = C.base + (long long)tgt * C.stride;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            ubo[f] = ubo[f] + A.scale * g[f];
+            A.ub[f * A.fstride + id] = ubo[f];
+        }
+        last_tgt = tgt;
+    };
     auto finish = [&](int tgt, const T apj[NC], const T amj[NC]) {
+        if constexpr (PACK) {
+            finish_pack(tgt, apj, amj);
+            return;
+        }
         double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -223,9 +305,9 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     T wp[NC][W], wm[NC][W], ap[NC][W], am[NC][W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        T u[5], fp[NC], fm[NC];
-        adj_load<T, DIR>(A, C, i_lo - R + 1 + j, u);
-        group_flux(u, fp, fm);
+        T u[5], v, P, fp[NC], fm[NC];
+        adj_state<T, DIR, PACK>(A, C, i_lo - R + 1 + j, u, v, P);
+        group_flux(u, v, P, fp, fm);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             wp[q][j] = fp[q];
@@ -237,7 +319,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     // loads run one face ahead: the weights of the next face's right cell and
     // the state of the next cell to enter the window are in flight while this
     // face is differentiated (positions past the segment stay in bounds)
-    T wl[NC], wn[NC], un[5];
+    T wl[NC], wn[NC], un[5], vn, Pn;
     {
         T w5[5];
         adj_weight<T, DIR>(A, C, i_lo, w5);
@@ -247,20 +329,21 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
 #pragma unroll
         for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
     }
-    adj_load<T, DIR>(A, C, i_lo + R + 1, un);
+    adj_state<T, DIR, PACK>(A, C, i_lo + R + 1, un, vn, Pn);
     for (int i = i_lo; i <= i_hi; ++i) {
         T wr[NC], unew[5];
 #pragma unroll
         for (int q = 0; q < NC; ++q) wr[q] = wn[q];
 #pragma unroll
         for (int f = 0; f < 5; ++f) unew[f] = un[f];
+        const T vnew = vn, Pnew = Pn;
         {
             T w5[5];
             adj_weight<T, DIR>(A, C, i + 2, w5);
 #pragma unroll
             for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
         }
-        adj_load<T, DIR>(A, C, i + R + 2, un);
+        adj_state<T, DIR, PACK>(A, C, i + R + 2, un, vn, Pn);
         int tgt = 0;
         const bool own = target(i - R + 1, tgt);
         if (own) fetch_cell(tgt);
@@ -298,7 +381,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
         }
         if (i < i_hi) {
             T fp[NC], fm[NC];
-            group_flux(unew, fp, fm);
+            group_flux(unew, vnew, Pnew, fp, fm);
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
 #pragma unroll
@@ -331,27 +414,45 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     }
 }
 
-template <class T, int ORDER, int DIR, int CLO>
+template <class T, int ORDER, int DIR, bool PACK, int CLO>
 __device__ __forceinline__ void adj_passes(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
     if constexpr (CLO < 5) {
         constexpr int GS = AdjGroup<T, ORDER>::value;
         constexpr int CHI = CLO + GS < 5 ? CLO + GS : 5;
-        adj_pass<T, ORDER, DIR, CLO, CHI>(A, C, k0, k1);
-        adj_passes<T, ORDER, DIR, CHI>(A, C, k0, k1);
+        adj_pass<T, ORDER, DIR, PACK, CLO, CHI>(A, C, k0, k1);
+        adj_passes<T, ORDER, DIR, PACK, CHI>(A, C, k0, k1);
     }
 }
 
-#ifndef RH_ADJ_MINB
-#define RH_ADJ_MINB 1
-#endif
+// Three waves per SIMD for the FP32 sweeps that read the recovery pack (their
+// register window fits in 168 VGPRs); the others take what the window needs.
+template <class T, bool PACK>
+struct AdjMinBlocks {
+    static constexpr int value = (sizeof(T) == 4 && PACK) ? 3 : 1;
+};
 
-template <class T, int ORDER, int DIR>
-__global__ void __launch_bounds__(256, RH_ADJ_MINB) adj_roll(AdjArgs<T> A) {
+template <class T, int ORDER, int DIR, bool PACK>
+__global__ void __launch_bounds__(256, (AdjMinBlocks<T, PACK>::value)) adj_roll(AdjArgs<T> A) {
     Column<T, DIR> C;
     if (!column_of<T, DIR>(A, blockIdx.x * 256u + threadIdx.x, C)) return;
     const int k0 = blockIdx.y * A.seg;
     const int k1 = min(k0 + A.seg, A.n[DIR]);
-    adj_passes<T, ORDER, DIR, 0>(A, C, k0, k1);
+    adj_passes<T, ORDER, DIR, PACK, 0>(A, C, k0, k1);
+}
+
+template <class T>
+__global__ void adj_pack(const T* __restrict__ u, T* __restrict__ pk, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const RecoveryPack o = recovery_pack((double)u[i], (double)u[n + i], (double)u[2 * n + i],
+                                             (double)u[3 * n + i]);
+        pk[i] = (T)o.kap;
+        pk[n + i] = (T)o.p;
+        pk[2 * n + i] = (T)o.kap_E;
+        pk[3 * n + i] = (T)o.kap_M2;
+        pk[4 * n + i] = (T)o.p_E;
+        pk[5 * n + i] = (T)o.p_M2;
+    }
 }
 
 // Square tiles of 256-byte rows through LDS (64 x 64 FP32, 32 x 32 FP64), so
@@ -364,7 +465,7 @@ struct TransposeTile {
 
 template <class T, bool INIT>
 __global__ void __launch_bounds__(256) transpose_xy(const T* __restrict__ in, T* out, int R, int C, int nz,
-                                                    long long fs, T a, const T* init, T s) {
+                                                    long long fs, Lin3<T> init, T s) {
     constexpr int TS = TransposeTile<T>::value, RS = 256 / TS;
     __shared__ T tile[TS][TS + 1];
     const int z = blockIdx.z % nz, f = blockIdx.z / nz;
@@ -387,8 +488,15 @@ __global__ void __launch_bounds__(256) transpose_xy(const T* __restrict__ in, T*
         const int c = c0 + k, r = r0 + tx;   // output row c, column r
         if (r < R && c < C) {
             const long long o = dbase + (long long)c * R + r;
-            const T v = s * tile[tx][k];
-            out[o] = INIT ? a * init[o] + v : v;
+            T v = s * tile[tx][k];
+            if (INIT) {
+                T acc = (T)0;
+                if (init.X1) acc += init.a1 * init.X1[o];
+                if (init.X2) acc += init.a2 * init.X2[o];
+                if (init.X3) acc += init.a3 * init.X3[o];
+                v = acc + v;
+            }
+            out[o] = v;
         }
     }
 }
@@ -432,24 +540,33 @@ hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s)
     const unsigned gy = (nd + a.seg - 1) / a.seg;
     const dim3 grid(gx, gy), block(256);
     if (dir != 1 && dir != 2) return hipErrorInvalidValue;
+    if (dir == 2 && !a.pk) return hipErrorInvalidValue;   // z always runs with the pack
     if (order == 5) {
-        if (dir == 1) adj_roll<T, 5, 1><<<grid, block, 0, s>>>(a);
-        else adj_roll<T, 5, 2><<<grid, block, 0, s>>>(a);
+        if (dir == 1 && !a.pk) adj_roll<T, 5, 1, false><<<grid, block, 0, s>>>(a);
+        else if (dir == 1) adj_roll<T, 5, 1, true><<<grid, block, 0, s>>>(a);
+        else adj_roll<T, 5, 2, true><<<grid, block, 0, s>>>(a);
     } else {
-        if (dir == 1) adj_roll<T, 7, 1><<<grid, block, 0, s>>>(a);
-        else adj_roll<T, 7, 2><<<grid, block, 0, s>>>(a);
+        if (dir == 1 && !a.pk) adj_roll<T, 7, 1, false><<<grid, block, 0, s>>>(a);
+        else if (dir == 1) adj_roll<T, 7, 1, true><<<grid, block, 0, s>>>(a);
+        else adj_roll<T, 7, 2, true><<<grid, block, 0, s>>>(a);
     }
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_transpose_xy(const T* in, T* out, int R, int C, int nz, long long fs, T a, const T* init,
-                               T s, hipStream_t st) {
+hipError_t launch_adjoint_pack(const T* u, T* pk, long long ncell, hipStream_t s) {
+    adj_pack<T><<<blocks_for(ncell), 256, 0, s>>>(u, pk, ncell);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_transpose_xy(const T* in, T* out, int R, int C, int nz, long long fs, Lin3<T> init, T s,
+                               hipStream_t st) {
     constexpr int TS = TransposeTile<T>::value;
     if ((long long)5 * nz > 65535) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((C + TS - 1) / TS), (unsigned)((R + TS - 1) / TS), (unsigned)(5 * nz));
-    if (init) transpose_xy<T, true><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, a, init, s);
-    else transpose_xy<T, false><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, a, init, s);
+    if (init.X1 || init.X2 || init.X3) transpose_xy<T, true><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, init, s);
+    else transpose_xy<T, false><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, init, s);
     return hipGetLastError();
 }
 
@@ -469,7 +586,8 @@ hipError_t launch_lincomb(T* out, long long n, T a, const T* X, T b, const T* Y,
 #define RH_ADJ_INSTANTIATE(T)                                                                      \
     template hipError_t launch_adjoint_sweep<T>(int, int, AdjArgs<T>, hipStream_t);               \
     template hipError_t launch_fill_zero<T>(T*, long long, hipStream_t);                          \
-    template hipError_t launch_transpose_xy<T>(const T*, T*, int, int, int, long long, T, const T*, T, \
+    template hipError_t launch_adjoint_pack<T>(const T*, T*, long long, hipStream_t);             \
+    template hipError_t launch_transpose_xy<T>(const T*, T*, int, int, int, long long, Lin3<T>, T,     \
                                                hipStream_t);                                       \
     template hipError_t launch_lincomb<T>(T*, long long, T, const T*, T, const T*, T, const T*, T, \
                                           const T*, hipStream_t);

@@ -203,6 +203,49 @@ __device__ __forceinline__ void recover_vp_grad(double E, double Mx, double My, 
     }
 }
 
+// Primitive recovery written as v = kappa(E, M^2) M and p = P(E, M^2), with the
+// four partial derivatives of kappa and P (FP64).  This covers the floors: below
+// the energy floor kappa = 0 and P = max(E, 0)/3; above the velocity cap M is
+// rescaled to |v| = 1 - delta, which makes kappa = K0/|M| and P = E delta/(1 +
+// sqrt(1 + 3 delta)) with constants from the closed form.
+struct RecoveryPack {
+    double kap, p, kap_E, kap_M2, p_E, p_M2;
+};
+
+__device__ __forceinline__ RecoveryPack recovery_pack(double E, double Mx, double My, double Mz) {
+    RecoveryPack o;
+    if (E < kEFloor) {
+        o.kap = 0.0;
+        o.p = (E > 0.0 ? E : 0.0) / 3.0;
+        o.kap_E = o.kap_M2 = o.p_M2 = 0.0;
+        o.p_E = E > 0.0 ? 1.0 / 3.0 : 0.0;
+        return o;
+    }
+    const double M2 = Mx * Mx + My * My + Mz * Mz;
+    const double cap = (1.0 - kVDelta) * E * E;
+    if (M2 > cap) {
+        const double q = sqrt(1.0 + 3.0 * kVDelta);
+        o.kap = 3.0 * sqrt(1.0 - kVDelta) / ((2.0 + q) * sqrt(M2));
+        o.p = E * kVDelta / (1.0 + q);
+        o.kap_E = 0.0;
+        o.kap_M2 = -0.5 * o.kap / M2;
+        o.p_E = kVDelta / (1.0 + q);
+        o.p_M2 = 0.0;
+        return o;
+    }
+    const double D = sqrt(4.0 * E * E - 3.0 * M2);
+    const double a = 2.0 * E + D, b = E + D;
+    const double r = fast_rcp(a * b * D);
+    const double ra = b * D * r, rb = a * D * r, rD = a * b * r;
+    o.kap = 3.0 * ra;
+    o.p = (E * E - M2) * rb;
+    o.kap_E = -(o.kap * o.kap / 3.0) * (2.0 + 4.0 * E * rD);
+    o.kap_M2 = 0.5 * o.kap * o.kap * rD;
+    o.p_E = (2.0 * E - o.p * (1.0 + 4.0 * E * rD)) * rb;
+    o.p_M2 = (1.5 * o.p * rD - 1.0) * rb;
+    return o;
+}
+
 // ub += (d f+ / du)^T ap + (d f- / du)^T am for one cell, f+- = (F_DIR(u) +- u)/2.
 template <class T, int DIR>
 __device__ __forceinline__ void split_flux_vjp(const T u[5], const T ap[5], const T am[5], T ub[5]) {

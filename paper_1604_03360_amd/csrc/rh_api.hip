@@ -929,13 +929,14 @@ rh_status rh_batch_kernel_times(rh_batch* b, double* ms_out, long long* launches
 // ===========================================================================
 namespace {
 
-// out = a init + s J(u)^T w (init may be null, meaning 0, and may alias out).
-// The x axis runs as a y sweep on x-y transposed copies of u and w (momentum
-// fields exchanged), so that its loads are coalesced; the transposed adjoint is
-// added back by the transpose that initialises out.  The bound workspace's
-// first three slots hold the transposed u, w and adjoint.
+// out = (a1 X1 + a2 X2 + a3 X3) + s J(u)^T w (null X terms are skipped; they may
+// alias out).  The x axis runs as a y sweep on x-y transposed copies of u and w
+// (momentum fields exchanged), so that its loads are coalesced; the transposed
+// adjoint is added back by the transpose that also forms the linear combination.
+// The bound workspace's three slots hold the transposed u, w and adjoint, then
+// the recovery pack of the y and z sweeps.
 template <class T>
-rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, T a, const T* init, T s) {
+rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, rh::Lin3<T> init, T s) {
     const long long N = 5 * p->ncell;
     const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
     const double h[3] = {p->d.dx, p->d.dy, p->d.dz};
@@ -952,17 +953,16 @@ rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, T a, co
         T* uT = (T*)p->ws;
         T* wT = uT + N;
         T* bT = uT + 2 * N;
-        auto tr = [&](const T* in, T* o, int R, int C, T aa, const T* ini, T ss) {
+        auto tr = [&](const T* in, T* o, int R, int C, rh::Lin3<T> ini, T ss) {
             return timed_launch(p, RH_KERNEL_OTHER, [&] {
-                return rh::launch_transpose_xy<T>(in, o, R, C, n[2], p->ncell, aa, ini, ss, p->stream);
+                return rh::launch_transpose_xy<T>(in, o, R, C, n[2], p->ncell, ini, ss, p->stream);
             }, "transpose launch");
         };
-        if ((st = tr(u, uT, n[1], n[0], (T)0, nullptr, (T)1)) != RH_OK) return st;
-        if ((st = tr(w, wT, n[1], n[0], (T)0, nullptr, (T)1)) != RH_OK) return st;
-        st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(bT, N, p->stream); },
-                          "fill launch");
-        if (st != RH_OK) return st;
+        const rh::Lin3<T> none = {(T)0, (T)0, (T)0, nullptr, nullptr, nullptr};
+        if ((st = tr(u, uT, n[1], n[0], none, (T)1)) != RH_OK) return st;
+        if ((st = tr(w, wT, n[1], n[0], none, (T)1)) != RH_OK) return st;
         rh::AdjArgs<T> x = base;
+        x.zero_init = 1;   // the transposed adjoint starts at zero
         x.u = uT;
         x.w = wT;
         x.ub = bT;
@@ -982,23 +982,30 @@ rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, T a, co
                           [&] { return rh::launch_adjoint_sweep<T>(1, p->d.scheme, x, p->stream); },
                           "adjoint sweep launch");
         if (st != RH_OK) return st;
-        if ((st = tr(bT, out, n[0], n[1], a, init, s)) != RH_OK) return st;
-    } else if (init) {
-        if (init != out || a != (T)1) {
-            st = timed_launch(p, RH_KERNEL_OTHER, [&] {
-                return rh::launch_lincomb<T>(out, N, a, init, (T)0, nullptr, (T)0, nullptr, (T)0, nullptr,
-                                             p->stream);
-            }, "combine launch");
-            if (st != RH_OK) return st;
-        }
+        if ((st = tr(bT, out, n[0], n[1], init, s)) != RH_OK) return st;
+    } else if (init.X1 || init.X2 || init.X3) {
+        st = timed_launch(p, RH_KERNEL_OTHER, [&] {
+            return rh::launch_lincomb<T>(out, N, init.a1, init.X1, init.a2, init.X2, init.a3, init.X3, (T)0,
+                                         nullptr, p->stream);
+        }, "combine launch");
+        if (st != RH_OK) return st;
     } else {
         st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(out, N, p->stream); },
                           "fill launch");
         if (st != RH_OK) return st;
     }
+    // the y and z sweeps read the recovery and its derivatives from a six-field
+    // pack in the workspace (the transposed copies are no longer needed)
+    T* pk = (T*)p->ws;
+    if (n[1] > 1 || n[2] > 1) {
+        st = timed_launch(p, RH_KERNEL_OTHER,
+                          [&] { return rh::launch_adjoint_pack<T>(u, pk, p->ncell, p->stream); }, "pack launch");
+        if (st != RH_OK) return st;
+    }
     for (int d = 1; d < 3; ++d) {
         if (n[d] < 2) continue;   // a one-cell axis contributes nothing to L
         rh::AdjArgs<T> q = base;
+        q.pk = pk;
         q.u = u;
         q.w = w;
         q.ub = out;
@@ -1026,21 +1033,17 @@ rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, T a, co
 template <class T>
 rh_status step_vjp_core(rh_plan* p, double t, double dt, const T* un, const T* u1, const T* u2, const T* bin,
                         T* bout, T* b2, T* b1) {
-    const size_t S = 5 * (size_t)p->ncell;
     const T td = (T)dt;
     rh_status st;
     // b2 = 2/3 b + 2/3 dt J(u2)^T b
-    if ((st = vjp_impl<T>(p, t + 0.5 * dt, u2, bin, b2, (T)(2.0 / 3.0), bin, (T)(2.0 / 3.0) * td)) != RH_OK)
-        return st;
+    const rh::Lin3<T> i2 = {(T)(2.0 / 3.0), (T)0, (T)0, bin, nullptr, nullptr};
+    if ((st = vjp_impl<T>(p, t + 0.5 * dt, u2, bin, b2, i2, (T)(2.0 / 3.0) * td)) != RH_OK) return st;
     // b1 = 1/4 b2 + 1/4 dt J(u1)^T b2
-    if ((st = vjp_impl<T>(p, t + dt, u1, b2, b1, (T)0.25, b2, (T)0.25 * td)) != RH_OK) return st;
+    const rh::Lin3<T> i1 = {(T)0.25, (T)0, (T)0, b2, nullptr, nullptr};
+    if ((st = vjp_impl<T>(p, t + dt, u1, b2, b1, i1, (T)0.25 * td)) != RH_OK) return st;
     // out = (1/3 b + 3/4 b2 + b1) + dt J(un)^T b1
-    st = timed_launch(p, RH_KERNEL_OTHER, [&] {
-        return rh::launch_lincomb<T>(bout, (long long)S, (T)(1.0 / 3.0), bin, (T)0.75, b2, (T)1, b1, (T)0,
-                                     nullptr, p->stream);
-    }, "combine launch");
-    if (st != RH_OK) return st;
-    return vjp_impl<T>(p, t, un, b1, bout, (T)1, bout, td);
+    const rh::Lin3<T> i0 = {(T)(1.0 / 3.0), (T)0.75, (T)1, bin, b2, b1};
+    return vjp_impl<T>(p, t, un, b1, bout, i0, td);
 }
 
 // The stage states are recomputed into scratch[0..1]; b2 goes to scratch[2]
@@ -1076,9 +1079,12 @@ rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void*
     if (overlaps(out, sb, u, sb) || overlaps(out, sb, w, sb)) return fail(RH_E_INVAL, "out aliases u or w");
     if (overlaps(p->ws, 3 * sb, u, sb) || overlaps(p->ws, 3 * sb, w, sb) || overlaps(p->ws, 3 * sb, out, sb))
         return fail(RH_E_INVAL, "an operand aliases the bound workspace");
-    return is_fp32(p) ? vjp_impl<float>(p, t, (const float*)u, (const float*)w, (float*)out, 0.0f, nullptr, 1.0f)
-                      : vjp_impl<double>(p, t, (const double*)u, (const double*)w, (double*)out, 0.0, nullptr,
-                                         1.0);
+    if (is_fp32(p)) {
+        const rh::Lin3<float> none = {0.0f, 0.0f, 0.0f, nullptr, nullptr, nullptr};
+        return vjp_impl<float>(p, t, (const float*)u, (const float*)w, (float*)out, none, 1.0f);
+    }
+    const rh::Lin3<double> none = {0.0, 0.0, 0.0, nullptr, nullptr, nullptr};
+    return vjp_impl<double>(p, t, (const double*)u, (const double*)w, (double*)out, none, 1.0);
 }
 
 rh_status rh_step_store(rh_plan* p, double dt, double* t_inout, void* stages) {
