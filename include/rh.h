@@ -106,7 +106,8 @@ void rh_plan_destroy(rh_plan* plan);
 size_t rh_state_bytes(const rh_plan* plan);
 
 /* Bytes of the workspace the caller must provide to rh_bind: the two
- * intermediate Runge-Kutta stage states and the L accumulator (3 states). */
+ * intermediate Runge-Kutta stage states and the L accumulator (3 states).  The
+ * adjoint calls use it as scratch (a six-field recovery pack). */
 size_t rh_workspace_bytes(const rh_plan* plan);
 
 /* Bind caller-owned device buffers and a stream.  state: rh_state_bytes bytes,
@@ -175,8 +176,8 @@ rh_status rh_kernel_times(rh_plan* plan, double* ms_out, long long* launches_out
 /* out = J(u)^T w, J = dL/du of Eq. (2) at state u and time t.  u, w and out are
  * device buffers of the plan precision and layout [5][nz][ny][nx]; out must
  * not alias u or w, and none of them may alias the bound workspace, whose
- * contents this call overwrites (it holds x-y transposed copies for the x
- * axis).  Asynchronous on the bound stream.  Errors: RH_E_STATE (unbound),
+ * contents this call overwrites (it holds the per-cell recovery pack).
+ * Asynchronous on the bound stream.  Errors: RH_E_STATE (unbound),
  * RH_E_INVAL (NULL or aliasing). */
 rh_status rh_apply_vjp(rh_plan* plan, double t, const void* u, const void* w, void* out);
 
@@ -189,7 +190,7 @@ size_t rh_vjp_workspace_bytes(const rh_plan* plan);
  *   b2 = 2/3 b + 2/3 dt J(u2)^T b,  b1 = 1/4 b2 + 1/4 dt J(u1)^T b2,
  *   ubar_out = 1/3 b + 3/4 b2 + b1 + dt J(u_n)^T b1   (b = ubar_in),
  * with J(u2) at t + dt/2, J(u1) at t + dt, J(u_n) at t.  The plan must be bound;
- * its workspace is overwritten (recomputation and transposed copies) and may
+ * its workspace is overwritten (recomputation and recovery pack) and may
  * not alias any operand.  ubar_out may alias ubar_in.  Errors: RH_E_STATE
  * (unbound), RH_E_INVAL. */
 rh_status rh_step_vjp(rh_plan* plan, double t, double dt, const void* u_n, const void* ubar_in,

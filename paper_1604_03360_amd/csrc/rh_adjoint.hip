@@ -1,15 +1,19 @@
 // rh_adjoint.hip -- gfx950 kernels of the adjoint of L and of the SSP-RK3 step.
 //
-// One adjoint sweep per axis.  Each lane owns a segment [k0, k1) of one grid
-// line along the sweep axis and rolls along it over every face whose stencil
-// reaches an owned position (the segment plus R faces on each side), keeping a
-// register window of 2R cells of split fluxes and of split-flux adjoints.  For
-// each face it adds the face weight g = (w_{i+1} - w_i)/h times the WENO
-// gradients to the window; a position leaving the window is complete and, if
-// the lane owns it, is mapped through the flux Jacobian and added to the
-// adjoint field.  Every cell (and every ghost position that copies it under
-// outflow boundaries) is owned by exactly one lane per sweep, so the
-// read-modify-write of the adjoint needs no atomics.
+// One adjoint sweep per axis, all reading a per-cell pack of the primitive
+// recovery and its derivatives (adj_pack, FP64 arithmetic).  The x sweep
+// (adj_x) stages LDS tiles of contiguous rows, differentiates each face once
+// and gathers the face partials per cell; it writes the output from the
+// caller's linear combination plus its part.  The y and z sweeps (adj_roll)
+// give each lane a segment [k0, k1) of one grid line; the lane rolls along it
+// over every face whose stencil reaches an owned position (the segment plus R
+// faces on each side), keeping a register window of 2R cells of split fluxes
+// and of split-flux adjoints; for each face it adds the face weight
+// g = (w_{i+1} - w_i)/h times the WENO gradients to the window, and a position
+// leaving the window is complete and, if the lane owns it, is mapped through
+// the flux Jacobian and added to the adjoint field.  Every cell (and every
+// ghost position that copies it under outflow boundaries) is owned by exactly
+// one lane per sweep, so the read-modify-write needs no atomics.
 #include "rh_internal.hpp"
 #include "rh_adjoint.hpp"
 #include "../../include/rh.h"
@@ -88,15 +92,14 @@ __device__ __forceinline__ void adj_load(const AdjArgs<T>& A, const Column<T, DI
     for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
 }
 
-// State at line position m with its velocity along the sweep axis and pressure:
-// from the recovery pack when one is given (interior, periodic and outflow
-// positions), else recovered here in FP64 (always for analytic ghosts).
-template <class T, int DIR, bool PACK>
+// State at line position m with its velocity along the sweep axis and pressure,
+// taken from the recovery pack (interior, periodic and outflow positions) or,
+// for analytic ghosts, evaluated and recovered here in FP64.
+template <class T, int DIR>
 __device__ __forceinline__ void adj_state(const AdjArgs<T>& A, const Column<T, DIR>& C, int m, T u[5], T& v,
                                           T& P) {
     const int nd = A.n[DIR];
     int mm = m;
-    bool analytic = false;
     if (m < 0 || m >= nd) {
         if (A.bc == RH_BC_PERIODIC) {
             mm = m % nd;
@@ -104,26 +107,20 @@ __device__ __forceinline__ void adj_state(const AdjArgs<T>& A, const Column<T, D
         } else if (A.bc == RH_BC_OUTFLOW) {
             mm = m < 0 ? 0 : nd - 1;
         } else {
-            analytic = true;
-        }
-    }
-    if (analytic) {
-        adj_load<T, DIR>(A, C, m, u);
-    } else {
-        const long long id = C.base + mm * C.stride;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
-        if constexpr (PACK) {
-            v = A.pk[id] * u[1 + DIR];
-            P = A.pk[A.fstride + id];
+            adj_load<T, DIR>(A, C, m, u);
+            double vd, pd;
+            unsigned dummy = 0;
+            recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, pd, dummy);
+            v = (T)vd;
+            P = (T)pd;
             return;
         }
     }
-    double vd, pd;
-    unsigned dummy = 0;
-    recover_vp<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, pd, dummy);
-    v = (T)vd;
-    P = (T)pd;
+    const long long id = C.base + mm * C.stride;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
+    v = A.pk[id] * u[1 + DIR];
+    P = A.pk[A.fstride + id];
 }
 
 // weights at line position m: zero outside the grid unless periodic
@@ -167,7 +164,7 @@ struct AdjGroup {
     static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? RH_ADJ_GROUP_F32_W5 : RH_ADJ_GROUP_OTHER;
 };
 
-template <class T, int ORDER, int DIR, bool PACK, int CLO, int CHI>
+template <class T, int ORDER, int DIR, int CLO, int CHI>
 __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R, NC = CHI - CLO;
     const int nd = A.n[DIR];
@@ -215,22 +212,17 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
         const long long id = C.base + (long long)tgt * C.stride;
 #pragma unroll
         for (int f = 0; f < 5; ++f) uf[f] = A.u[f * A.fstride + id];
-        if constexpr (PACK && CHI > 1) {
+        if constexpr (CHI > 1) {
             pkf[0] = A.pk[id];
 #pragma unroll
             for (int q = 1; q < 5; ++q) pkf[q] = A.pk[(q + 1) * A.fstride + id];
         }
         if (tgt == last_tgt) return;
-        if (CLO == 0 && A.zero_init) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) ubo[f] = (T)0;
-            return;
-        }
 #pragma unroll
         for (int f = 0; f < 5; ++f) ubo[f] = A.ub[f * A.fstride + id];
     };
     // ub += scale * sum over the group of (d f+_c/du)^T a+_c + (d f-_c/du)^T a-_c
-    auto finish_pack = [&](int tgt, const T apj[NC], const T amj[NC]) {
+    auto finish = [&](int tgt, const T apj[NC], const T amj[NC]) {
         // pkf = (kappa, dkappa/dE, dkappa/dM2, dP/dE, dP/dM2); v_d = kappa M_d
         T lam[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, g[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
 #pragma unroll
@@ -264,49 +256,11 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
         }
         last_tgt = tgt;
     };
-    auto finish = [&](int tgt, const T apj[NC], const T amj[NC]) {
-        if constexpr (PACK) {
-            finish_pack(tgt, apj, amj);
-            return;
-        }
-        double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dl[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-            lam[CLO + q] = 0.5 * ((double)apj[q] + (double)amj[q]);
-            dl[CLO + q] = 0.5 * ((double)apj[q] - (double)amj[q]);
-        }
-        double g[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) g[c] = dl[c];
-        g[1 + DIR] += lam[0];
-        if constexpr (CHI > 1) {
-            double vd, pd, gv[4], gp[4];
-            recover_vp_grad<DIR>((double)uf[0], (double)uf[1], (double)uf[2], (double)uf[3], vd, pd, gv, gp);
-            // F_c = M_c v + p delta(c, 1+DIR) (c = 1..3), F_4 = N v
-            double S = 0.0;
-#pragma unroll
-            for (int c = (CLO > 1 ? CLO : 1); c < CHI; ++c) {
-                S += lam[c] * (double)uf[c];
-                g[c] += lam[c] * vd;
-            }
-            const double lp = lam[1 + DIR];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) g[m] += S * gv[m] + lp * gp[m];
-        }
-        const long long id = C.base + (long long)tgt * C.stride;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            ubo[f] = ubo[f] + A.scale * (T)g[f];
-            A.ub[f * A.fstride + id] = ubo[f];
-        }
-        last_tgt = tgt;
-    };
-
     T wp[NC][W], wm[NC][W], ap[NC][W], am[NC][W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         T u[5], v, P, fp[NC], fm[NC];
-        adj_state<T, DIR, PACK>(A, C, i_lo - R + 1 + j, u, v, P);
+        adj_state<T, DIR>(A, C, i_lo - R + 1 + j, u, v, P);
         group_flux(u, v, P, fp, fm);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -329,7 +283,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
 #pragma unroll
         for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
     }
-    adj_state<T, DIR, PACK>(A, C, i_lo + R + 1, un, vn, Pn);
+    adj_state<T, DIR>(A, C, i_lo + R + 1, un, vn, Pn);
     for (int i = i_lo; i <= i_hi; ++i) {
         T wr[NC], unew[5];
 #pragma unroll
@@ -343,7 +297,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
 #pragma unroll
             for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
         }
-        adj_state<T, DIR, PACK>(A, C, i + R + 2, un, vn, Pn);
+        adj_state<T, DIR>(A, C, i + R + 2, un, vn, Pn);
         int tgt = 0;
         const bool own = target(i - R + 1, tgt);
         if (own) fetch_cell(tgt);
@@ -414,30 +368,30 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     }
 }
 
-template <class T, int ORDER, int DIR, bool PACK, int CLO>
+template <class T, int ORDER, int DIR, int CLO>
 __device__ __forceinline__ void adj_passes(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
     if constexpr (CLO < 5) {
         constexpr int GS = AdjGroup<T, ORDER>::value;
         constexpr int CHI = CLO + GS < 5 ? CLO + GS : 5;
-        adj_pass<T, ORDER, DIR, PACK, CLO, CHI>(A, C, k0, k1);
-        adj_passes<T, ORDER, DIR, PACK, CHI>(A, C, k0, k1);
+        adj_pass<T, ORDER, DIR, CLO, CHI>(A, C, k0, k1);
+        adj_passes<T, ORDER, DIR, CHI>(A, C, k0, k1);
     }
 }
 
-// Three waves per SIMD for the FP32 sweeps that read the recovery pack (their
-// register window fits in 168 VGPRs); the others take what the window needs.
-template <class T, bool PACK>
+// Three waves per SIMD for FP32 (the register window fits in 168 VGPRs); FP64
+// takes what the window needs.
+template <class T>
 struct AdjMinBlocks {
-    static constexpr int value = (sizeof(T) == 4 && PACK) ? 3 : 1;
+    static constexpr int value = sizeof(T) == 4 ? 3 : 1;
 };
 
-template <class T, int ORDER, int DIR, bool PACK>
-__global__ void __launch_bounds__(256, (AdjMinBlocks<T, PACK>::value)) adj_roll(AdjArgs<T> A) {
+template <class T, int ORDER, int DIR>
+__global__ void __launch_bounds__(256, (AdjMinBlocks<T>::value)) adj_roll(AdjArgs<T> A) {
     Column<T, DIR> C;
     if (!column_of<T, DIR>(A, blockIdx.x * 256u + threadIdx.x, C)) return;
     const int k0 = blockIdx.y * A.seg;
     const int k1 = min(k0 + A.seg, A.n[DIR]);
-    adj_passes<T, ORDER, DIR, PACK, 0>(A, C, k0, k1);
+    adj_passes<T, ORDER, DIR, 0>(A, C, k0, k1);
 }
 
 template <class T>
@@ -455,50 +409,247 @@ __global__ void adj_pack(const T* __restrict__ u, T* __restrict__ pk, long long 
     }
 }
 
-// Square tiles of 256-byte rows through LDS (64 x 64 FP32, 32 x 32 FP64), so
-// that every read and write of a wave is a contiguous 256-byte run.  init may
-// alias out (each element is read and written by the same lane).
+// ---------------------------------------------------------------------------
+// x axis: x is contiguous, so a block takes a tile of TX cells x TY rows plus
+// ghosts in LDS, as the forward x sweep does.  Per component, each lane
+// differentiates one face (the tile's faces are spread over the lanes) and
+// writes the face's stencil partials to LDS; after a barrier each lane sums
+// the partials of the faces that reach its cell in a fixed order.  With all
+// five split-flux adjoints of its cell in registers the lane applies the flux
+// Jacobian once and writes out = (linear combination of init terms) + scale g.
+// Outflow ghost positions fold onto the edge cells (same state, so their
+// split-flux adjoints add before the Jacobian); analytic ghosts are constants.
+// ---------------------------------------------------------------------------
 template <class T>
-struct TransposeTile {
-    static constexpr int value = 256 / sizeof(T);
-};
-
-template <class T, bool INIT>
-__global__ void __launch_bounds__(256) transpose_xy(const T* __restrict__ in, T* out, int R, int C, int nz,
-                                                    long long fs, Lin3<T> init, T s) {
-    constexpr int TS = TransposeTile<T>::value, RS = 256 / TS;
-    __shared__ T tile[TS][TS + 1];
-    const int z = blockIdx.z % nz, f = blockIdx.z / nz;
-    const int fo = f == 1 ? 2 : (f == 2 ? 1 : f);
-    const long long plane = (long long)R * C;
-    const T* src = in + f * fs + z * plane;
-    const long long dbase = fo * fs + z * plane;
-    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-    const int c0 = blockIdx.x * TS, r0 = blockIdx.y * TS;
+__device__ __forceinline__ void x_state(const AdjArgs<T>& A, int gx, int row, T u[5], T& v, T& P) {
+    const int nx = A.n[0];
+    int mx = gx;
+    if (gx < 0 || gx >= nx) {
+        if (A.bc == RH_BC_PERIODIC) {
+            mx = gx % nx;
+            if (mx < 0) mx += nx;
+        } else if (A.bc == RH_BC_OUTFLOW) {
+            mx = gx < 0 ? 0 : nx - 1;
+        } else {
+            const int y = row % A.n[1], z = row / A.n[1];
+            double uh[5];
+            hubble_conserved(A.hb, A.hb.c0[0] + gx * A.hb.h[0], A.hb.c0[1] + y * A.hb.h[1],
+                             A.hb.c0[2] + z * A.hb.h[2], uh);
 #pragma unroll
-    for (int kk = 0; kk < TS / RS; ++kk) {
-        const int k = ty + kk * RS;
-        const int r = r0 + k, c = c0 + tx;
-        if (r < R && c < C) tile[k][tx] = src[(long long)r * C + c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TS / RS; ++kk) {
-        const int k = ty + kk * RS;
-        const int c = c0 + k, r = r0 + tx;   // output row c, column r
-        if (r < R && c < C) {
-            const long long o = dbase + (long long)c * R + r;
-            T v = s * tile[tx][k];
-            if (INIT) {
-                T acc = (T)0;
-                if (init.X1) acc += init.a1 * init.X1[o];
-                if (init.X2) acc += init.a2 * init.X2[o];
-                if (init.X3) acc += init.a3 * init.X3[o];
-                v = acc + v;
-            }
-            out[o] = v;
+            for (int f = 0; f < 5; ++f) u[f] = (T)uh[f];
+            double vd, pd;
+            unsigned dummy = 0;
+            recover_vp<0>(uh[0], uh[1], uh[2], uh[3], vd, pd, dummy);
+            v = (T)vd;
+            P = (T)pd;
+            return;
         }
     }
+    const long long id = mx + (long long)nx * row;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
+    v = A.pk[id] * u[1];
+    P = A.pk[A.fstride + id];
+}
+
+template <class T, int ORDER, int TX, int TY>
+__global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
+    constexpr int R = (ORDER + 1) / 2, K = 2 * R - 1;
+    constexpr int CPL = TX * TY / 256;   // cells per lane
+    constexpr int NF = TX + 2 * R - 1;   // faces x0-R .. x0+TX+R-2 (face i: between cells i and i+1)
+    constexpr int NC = TX + 4 * R - 2;   // cells x0-2R+1 .. x0+TX+2R-2
+    constexpr int NW = TX + 2 * R;       // weights x0-R .. x0+TX+R-1
+    static_assert(TX * TY % 256 == 0, "whole cells per lane");
+    __shared__ T sfp[5][TY][NC];
+    __shared__ T sfm[5][TY][NC];
+    __shared__ T sw[5][TY][NW];
+    __shared__ T sp[TY][NF][K];          // plus partials of face fl for cells fl .. fl+K-1 (local)
+    __shared__ T sm[TY][NF][K];          // minus partials of face fl for cells fl+1 .. fl+K
+    const int nx = A.n[0];
+    const int nrows = A.n[1] * A.n[2];
+    const int ntx = (nx + TX - 1) / TX;
+    const int bx = blockIdx.x % ntx, by = blockIdx.x / ntx;
+    const int x0 = bx * TX, r0 = by * TY;
+    const int tid = threadIdx.x;
+    const bool periodic = A.bc == RH_BC_PERIODIC;
+    const T half = (T)0.5;
+
+    for (int idx = tid; idx < TY * NC; idx += 256) {
+        const int ly = idx / NC, lx = idx - ly * NC;
+        const int row = r0 + ly;
+        T fp[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, fm[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+        if (row < nrows) {
+            T u[5], v, P;
+            x_state<T>(A, x0 - 2 * R + 1 + lx, row, u, v, P);
+            T f[5];
+            f[0] = u[1];
+            f[1] = u[1] * v + P;
+            f[2] = u[2] * v;
+            f[3] = u[3] * v;
+            f[4] = u[4] * v;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                fp[c] = half * (f[c] + u[c]);
+                fm[c] = half * (f[c] - u[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            sfp[c][ly][lx] = fp[c];
+            sfm[c][ly][lx] = fm[c];
+        }
+    }
+    for (int idx = tid; idx < TY * NW; idx += 256) {
+        const int ly = idx / NW, lx = idx - ly * NW;
+        const int row = r0 + ly;
+        int gx = x0 - R + lx;
+        bool inside = row < nrows;
+        if (inside && (gx < 0 || gx >= nx)) {
+            if (periodic) {
+                gx %= nx;
+                if (gx < 0) gx += nx;
+            } else {
+                inside = false;   // weights vanish outside a non-periodic grid
+            }
+        }
+        const long long id = gx + (long long)nx * row;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sw[c][ly][lx] = inside ? A.w[c * A.fstride + id] : (T)0;
+    }
+    __syncthreads();
+
+    T ap[CPL][5], am[CPL][5];
+#pragma unroll 1
+    for (int c = 0; c < 5; ++c) {
+        for (int f = tid; f < TY * NF; f += 256) {
+            const int fy = f / NF, fl = f - fy * NF;
+            const int i = x0 - R + fl;
+            T op[K], om[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) op[k] = om[k] = (T)0;
+            if ((periodic || (i >= -1 && i <= nx - 1)) && r0 + fy < nrows) {
+                const T g = (sw[c][fy][fl + 1] - sw[c][fy][fl]) * A.inv_h;
+                if constexpr (ORDER == 5) {
+                    weno5_grad_acc<T>(sfp[c][fy][fl], sfp[c][fy][fl + 1], sfp[c][fy][fl + 2], sfp[c][fy][fl + 3],
+                                      sfp[c][fy][fl + 4], (T)4 * A.eps, g, op[0], op[1], op[2], op[3], op[4]);
+                    weno5_grad_acc<T>(sfm[c][fy][fl + 5], sfm[c][fy][fl + 4], sfm[c][fy][fl + 3],
+                                      sfm[c][fy][fl + 2], sfm[c][fy][fl + 1], (T)4 * A.eps, g, om[4], om[3],
+                                      om[2], om[1], om[0]);
+                } else {
+                    T sv[7], o[7];
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) {
+                        sv[j] = sfp[c][fy][fl + j];
+                        o[j] = (T)0;
+                    }
+                    weno7_grad_acc<T>(sv, A.eps, g, o);
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) op[j] = o[j];
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) {
+                        sv[j] = sfm[c][fy][fl + 7 - j];
+                        o[j] = (T)0;
+                    }
+                    weno7_grad_acc<T>(sv, A.eps, g, o);
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) om[6 - j] = o[j];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                sp[fy][fl][k] = op[k];
+                sm[fy][fl][k] = om[k];
+            }
+        }
+        __syncthreads();
+        // partials reaching staged cell q: plus from faces q-k, minus from faces q-1-k
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int cell = tid + 256 * j, lx = cell % TX, ly = cell / TX;
+            const int q = lx + 2 * R - 1;   // every face reaching an owned cell is in the tile
+            T a_p = (T)0, a_m = (T)0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                a_p += sp[ly][q - k][k];
+                a_m += sm[ly][q - 1 - k][k];
+            }
+            const int gx = x0 + lx;
+            if (A.bc == RH_BC_OUTFLOW && (gx == 0 || gx == nx - 1) && r0 + ly < nrows) {
+                // ghost positions beyond the edge fold onto the edge cell
+                for (int e = 1; e < 2 * R; ++e) {
+                    const int qe = gx == 0 ? q - e : q + e;
+                    for (int k = 0; k < K; ++k) {
+                        const int fp_ = qe - k, fm_ = qe - 1 - k;
+                        if (fp_ >= 0 && fp_ < NF) a_p += sp[ly][fp_][k];
+                        if (fm_ >= 0 && fm_ < NF) a_m += sm[ly][fm_][k];
+                    }
+                }
+            }
+            ap[j][c] = a_p;
+            am[j][c] = a_m;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int cell = tid + 256 * j, lx = cell % TX, ly = cell / TX;
+        const int gx = x0 + lx, row = r0 + ly;
+        if (gx >= nx || row >= nrows) continue;
+        const long long id = gx + (long long)nx * row;
+        T uf[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) uf[f] = A.u[f * A.fstride + id];
+        const T kap = A.pk[id], kE = A.pk[2 * A.fstride + id], kM2 = A.pk[3 * A.fstride + id];
+        const T pE = A.pk[4 * A.fstride + id], pM2 = A.pk[5 * A.fstride + id];
+        T lam[5], g[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            lam[c] = half * (ap[j][c] + am[j][c]);
+            g[c] = half * (ap[j][c] - am[j][c]);
+        }
+        // F = (Mx, Mx v + p, My v, Mz v, N v) with v = kappa Mx
+        const T Mx = uf[1], vd = kap * Mx;
+        g[1] += lam[0];
+        T S = (T)0;
+#pragma unroll
+        for (int c = 1; c < 5; ++c) {
+            S += lam[c] * uf[c];
+            g[c] += lam[c] * vd;
+        }
+        const T lp = lam[1];
+        g[0] += S * (Mx * kE) + lp * pE;
+        const T sk = (T)2 * S * Mx * kM2, spp = (T)2 * lp * pM2;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) g[1 + m] += (sk + spp) * uf[1 + m];
+        g[1] += S * kap;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            const long long o = f * A.fstride + id;
+            T acc = (T)0;
+            if (init.X1) acc += init.a1 * init.X1[o];
+            if (init.X2) acc += init.a2 * init.X2[o];
+            if (init.X3) acc += init.a3 * init.X3[o];
+            A.ub[o] = acc + A.scale * g[f];
+        }
+    }
+}
+
+// Tile of the x adjoint: the narrowest of 64, 32, 16 cells that wastes the
+// least on a ragged row end (2R - 1 halo faces per row).  A 128 x 4 tile with
+// two cells per lane halves the idle lanes of the last face round but needs
+// twice the LDS; it measured 24% slower at 256^3 FP32.
+int adjoint_tile_x(int nx) {
+    int best = 64;
+    double best_cost = 1e300;
+    for (int tx : {64, 32, 16}) {
+        const int ntx = (nx + tx - 1) / tx;
+        const double cost = ntx * (tx + 5.0) / nx;
+        if (cost < best_cost - 1e-12) {
+            best_cost = cost;
+            best = tx;
+        }
+    }
+    return best;
 }
 
 template <class T>
@@ -539,16 +690,33 @@ hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s)
     a.seg = choose_segment(nd, (int)(gx * 256));
     const unsigned gy = (nd + a.seg - 1) / a.seg;
     const dim3 grid(gx, gy), block(256);
-    if (dir != 1 && dir != 2) return hipErrorInvalidValue;
-    if (dir == 2 && !a.pk) return hipErrorInvalidValue;   // z always runs with the pack
+    if ((dir != 1 && dir != 2) || !a.pk) return hipErrorInvalidValue;
     if (order == 5) {
-        if (dir == 1 && !a.pk) adj_roll<T, 5, 1, false><<<grid, block, 0, s>>>(a);
-        else if (dir == 1) adj_roll<T, 5, 1, true><<<grid, block, 0, s>>>(a);
-        else adj_roll<T, 5, 2, true><<<grid, block, 0, s>>>(a);
+        if (dir == 1) adj_roll<T, 5, 1><<<grid, block, 0, s>>>(a);
+        else adj_roll<T, 5, 2><<<grid, block, 0, s>>>(a);
     } else {
-        if (dir == 1 && !a.pk) adj_roll<T, 7, 1, false><<<grid, block, 0, s>>>(a);
-        else if (dir == 1) adj_roll<T, 7, 1, true><<<grid, block, 0, s>>>(a);
-        else adj_roll<T, 7, 2, true><<<grid, block, 0, s>>>(a);
+        if (dir == 1) adj_roll<T, 7, 1><<<grid, block, 0, s>>>(a);
+        else adj_roll<T, 7, 2><<<grid, block, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_adjoint_x(int order, AdjArgs<T> a, Lin3<T> init, hipStream_t s) {
+    if (!a.pk) return hipErrorInvalidValue;
+    const int tx = adjoint_tile_x(a.n[0]);
+    const int ty = tx == 64 ? 4 : 256 / tx;
+    const long long ntx = (a.n[0] + tx - 1) / tx;
+    const long long nrt = ((long long)a.n[1] * a.n[2] + ty - 1) / ty;
+    const dim3 grid((unsigned)(ntx * nrt));
+    if (order == 5) {
+        if (tx == 64) adj_x<T, 5, 64, 4><<<grid, 256, 0, s>>>(a, init);
+        else if (tx == 32) adj_x<T, 5, 32, 8><<<grid, 256, 0, s>>>(a, init);
+        else adj_x<T, 5, 16, 16><<<grid, 256, 0, s>>>(a, init);
+    } else {
+        if (tx == 64) adj_x<T, 7, 64, 4><<<grid, 256, 0, s>>>(a, init);
+        else if (tx == 32) adj_x<T, 7, 32, 8><<<grid, 256, 0, s>>>(a, init);
+        else adj_x<T, 7, 16, 16><<<grid, 256, 0, s>>>(a, init);
     }
     return hipGetLastError();
 }
@@ -556,17 +724,6 @@ hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s)
 template <class T>
 hipError_t launch_adjoint_pack(const T* u, T* pk, long long ncell, hipStream_t s) {
     adj_pack<T><<<blocks_for(ncell), 256, 0, s>>>(u, pk, ncell);
-    return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_transpose_xy(const T* in, T* out, int R, int C, int nz, long long fs, Lin3<T> init, T s,
-                               hipStream_t st) {
-    constexpr int TS = TransposeTile<T>::value;
-    if ((long long)5 * nz > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((C + TS - 1) / TS), (unsigned)((R + TS - 1) / TS), (unsigned)(5 * nz));
-    if (init.X1 || init.X2 || init.X3) transpose_xy<T, true><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, init, s);
-    else transpose_xy<T, false><<<grid, 256, 0, st>>>(in, out, R, C, nz, fs, init, s);
     return hipGetLastError();
 }
 
@@ -587,8 +744,7 @@ hipError_t launch_lincomb(T* out, long long n, T a, const T* X, T b, const T* Y,
     template hipError_t launch_adjoint_sweep<T>(int, int, AdjArgs<T>, hipStream_t);               \
     template hipError_t launch_fill_zero<T>(T*, long long, hipStream_t);                          \
     template hipError_t launch_adjoint_pack<T>(const T*, T*, long long, hipStream_t);             \
-    template hipError_t launch_transpose_xy<T>(const T*, T*, int, int, int, long long, Lin3<T>, T,     \
-                                               hipStream_t);                                       \
+    template hipError_t launch_adjoint_x<T>(int, AdjArgs<T>, Lin3<T>, hipStream_t);                \
     template hipError_t launch_lincomb<T>(T*, long long, T, const T*, T, const T*, T, const T*, T, \
                                           const T*, hipStream_t);
 

@@ -6,7 +6,8 @@
 // built face by face: the gradient of each WENO reconstruction (Sec. 1.2) with
 // respect to its stencil, scaled by g, is accumulated on the stencil cells, and
 // each cell's accumulated split-flux adjoints a+- are mapped through the split
-// f+- = (F(u) +- u)/2 and the flux Jacobian of F (primitive recovery included).
+// f+- = (F(u) +- u)/2 and the flux Jacobian of F, whose primitive-recovery part
+// comes from the per-cell pack below.
 #pragma once
 #include "rh_device.hpp"
 
@@ -131,78 +132,6 @@ __device__ __forceinline__ void weno7_grad_acc(const T s[7], T eps, T gbar, T o[
     for (int j = 0; j < 7; ++j) o[j] += gbar * d[j];
 }
 
-// Velocity along DIR and pressure of the closed-form recovery with their
-// gradients with respect to (E, Mx, My, Mz) (N does not enter), including the
-// two floors: below the energy floor v = 0, p = max(E, 0)/3; above the momentum
-// cap M is replaced by sqrt(1 - kVDelta) E M/|M| before the closed form.
-template <int DIR>
-__device__ __forceinline__ void recover_vp_grad(double E, double Mx, double My, double Mz, double& vd,
-                                                double& p, double gv[4], double gp[4]) {
-    for (int q = 0; q < 4; ++q) gv[q] = gp[q] = 0.0;
-    if (E < kEFloor) {
-        vd = 0.0;
-        p = (E > 0.0 ? E : 0.0) / 3.0;
-        gp[0] = E > 0.0 ? 1.0 / 3.0 : 0.0;
-        return;
-    }
-    double M[3] = {Mx, My, Mz};
-    double M2 = Mx * Mx + My * My + Mz * Mz;
-    const double cap = (1.0 - kVDelta) * E * E;
-    const bool capped = M2 > cap;
-    double Me[3] = {M[0], M[1], M[2]};
-    double absM = 0.0, absM3 = 0.0;
-    if (capped) {
-        absM = sqrt(M2);
-        absM3 = absM * M2;
-        const double s = sqrt(cap / M2);
-        for (int i = 0; i < 3; ++i) Me[i] = M[i] * s;
-        M2 = cap;
-    }
-    const double D = sqrt(4.0 * E * E - 3.0 * M2);
-    const double a = 2.0 * E + D, b = E + D;
-    // 1/a, 1/b and 1/D from one refined reciprocal of a b D (D >= E > 0 here)
-    const double r = fast_rcp(a * b * D);
-    const double ra = b * D * r, rb = a * D * r, rD = a * b * r;
-    const double k = 3.0 * ra;
-    vd = k * Me[DIR];
-    p = (E * E - M2) * rb;
-    // gradients with respect to (E, Me)
-    const double dk_dE = -(k * ra) * (2.0 + 4.0 * E * rD);
-    double gve[4], gpe[4];
-    gve[0] = Me[DIR] * dk_dE;
-    gpe[0] = (2.0 * E - p * (1.0 + 4.0 * E * rD)) * rb;
-    const double kk = 3.0 * k * ra * rD, pp = (3.0 * p * rD - 2.0) * rb;
-    for (int i = 0; i < 3; ++i) {
-        gve[1 + i] = (i == DIR ? k : 0.0) + Me[DIR] * (kk * Me[i]);
-        gpe[1 + i] = Me[i] * pp;
-    }
-    if (!capped) {
-        for (int q = 0; q < 4; ++q) {
-            gv[q] = gve[q];
-            gp[q] = gpe[q];
-        }
-        return;
-    }
-    // chain through Me_i = c E M_i / |M|, c = sqrt(1 - kVDelta)
-    const double c = sqrt(1.0 - kVDelta);
-    gv[0] = gve[0];
-    gp[0] = gpe[0];
-    for (int i = 0; i < 3; ++i) {
-        gv[0] += gve[1 + i] * c * M[i] / absM;
-        gp[0] += gpe[1 + i] * c * M[i] / absM;
-    }
-    for (int j = 0; j < 3; ++j) {
-        double sv = 0.0, sp = 0.0;
-        for (int i = 0; i < 3; ++i) {
-            const double dMe = c * E * ((i == j ? 1.0 : 0.0) / absM - M[i] * M[j] / absM3);
-            sv += gve[1 + i] * dMe;
-            sp += gpe[1 + i] * dMe;
-        }
-        gv[1 + j] = sv;
-        gp[1 + j] = sp;
-    }
-}
-
 // Primitive recovery written as v = kappa(E, M^2) M and p = P(E, M^2), with the
 // four partial derivatives of kappa and P (FP64).  This covers the floors: below
 // the energy floor kappa = 0 and P = max(E, 0)/3; above the velocity cap M is
@@ -244,27 +173,6 @@ __device__ __forceinline__ RecoveryPack recovery_pack(double E, double Mx, doubl
     o.p_E = (2.0 * E - o.p * (1.0 + 4.0 * E * rD)) * rb;
     o.p_M2 = (1.5 * o.p * rD - 1.0) * rb;
     return o;
-}
-
-// ub += (d f+ / du)^T ap + (d f- / du)^T am for one cell, f+- = (F_DIR(u) +- u)/2.
-template <class T, int DIR>
-__device__ __forceinline__ void split_flux_vjp(const T u[5], const T ap[5], const T am[5], T ub[5]) {
-    double vd, p, gv[4], gp[4];
-    recover_vp_grad<DIR>((double)u[0], (double)u[1], (double)u[2], (double)u[3], vd, p, gv, gp);
-    double lam[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) lam[c] = 0.5 * ((double)ap[c] + (double)am[c]);
-    // F = (M_d, Mx v + p dx, My v + p dy, Mz v + p dz, N v)
-    const double S = lam[1] * (double)u[1] + lam[2] * (double)u[2] + lam[3] * (double)u[3] +
-                     lam[4] * (double)u[4];
-    double g[5];
-    g[0] = S * gv[0] + lam[1 + DIR] * gp[0];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) g[1 + i] = lam[1 + i] * vd + S * gv[1 + i] + lam[1 + DIR] * gp[1 + i];
-    g[1 + DIR] += lam[0];
-    g[4] = lam[4] * vd;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) ub[c] += (T)(g[c] + 0.5 * ((double)ap[c] - (double)am[c]));
 }
 
 }  // namespace rh

@@ -930,97 +930,63 @@ rh_status rh_batch_kernel_times(rh_batch* b, double* ms_out, long long* launches
 namespace {
 
 // out = (a1 X1 + a2 X2 + a3 X3) + s J(u)^T w (null X terms are skipped; they may
-// alias out).  The x axis runs as a y sweep on x-y transposed copies of u and w
-// (momentum fields exchanged), so that its loads are coalesced; the transposed
-// adjoint is added back by the transpose that also forms the linear combination.
-// The bound workspace's three slots hold the transposed u, w and adjoint, then
-// the recovery pack of the y and z sweeps.
+// alias out).  The recovery pack of u (six fields) goes to the bound workspace;
+// the x-axis kernel writes out from the linear combination and its own part,
+// the y and z sweeps add theirs.
 template <class T>
 rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, rh::Lin3<T> init, T s) {
     const long long N = 5 * p->ncell;
     const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
     const double h[3] = {p->d.dx, p->d.dy, p->d.dz};
+    T* pk = (T*)p->ws;
     rh::AdjArgs<T> base;
     std::memset(&base, 0, sizeof(base));
+    base.u = u;
+    base.w = w;
+    base.ub = out;
+    base.pk = pk;
     base.fstride = p->ncell;
+    base.n[0] = n[0];
+    base.n[1] = n[1];
+    base.n[2] = n[2];
     base.eps = (T)(p->d.weno_eps > 0.0 ? p->d.weno_eps : 1e-6);
+    base.scale = s;
     base.hb.t = t;
     base.hb.t0 = p->d.hubble_t0;
     base.hb.e0 = p->d.hubble_e0;
     base.hb.n0 = p->d.hubble_n0;
-    rh_status st = RH_OK;
+    base.hb.c0[0] = p->d.x0;
+    base.hb.c0[1] = p->d.y0;
+    base.hb.c0[2] = p->d.z0;
+    base.hb.h[0] = h[0];
+    base.hb.h[1] = h[1];
+    base.hb.h[2] = h[2];
+    rh_status st = timed_launch(p, RH_KERNEL_OTHER,
+                                [&] { return rh::launch_adjoint_pack<T>(u, pk, p->ncell, p->stream); },
+                                "pack launch");
+    if (st != RH_OK) return st;
     if (n[0] > 1) {
-        T* uT = (T*)p->ws;
-        T* wT = uT + N;
-        T* bT = uT + 2 * N;
-        auto tr = [&](const T* in, T* o, int R, int C, rh::Lin3<T> ini, T ss) {
-            return timed_launch(p, RH_KERNEL_OTHER, [&] {
-                return rh::launch_transpose_xy<T>(in, o, R, C, n[2], p->ncell, ini, ss, p->stream);
-            }, "transpose launch");
-        };
-        const rh::Lin3<T> none = {(T)0, (T)0, (T)0, nullptr, nullptr, nullptr};
-        if ((st = tr(u, uT, n[1], n[0], none, (T)1)) != RH_OK) return st;
-        if ((st = tr(w, wT, n[1], n[0], none, (T)1)) != RH_OK) return st;
         rh::AdjArgs<T> x = base;
-        x.zero_init = 1;   // the transposed adjoint starts at zero
-        x.u = uT;
-        x.w = wT;
-        x.ub = bT;
-        x.n[0] = n[1];
-        x.n[1] = n[0];
-        x.n[2] = n[2];
         x.bc = p->d.bc[0];
         x.inv_h = (T)(1.0 / h[0]);
-        x.scale = (T)1;
-        x.hb.c0[0] = p->d.y0;
-        x.hb.c0[1] = p->d.x0;
-        x.hb.c0[2] = p->d.z0;
-        x.hb.h[0] = h[1];
-        x.hb.h[1] = h[0];
-        x.hb.h[2] = h[2];
         st = timed_launch(p, RH_KERNEL_ADJOINT,
-                          [&] { return rh::launch_adjoint_sweep<T>(1, p->d.scheme, x, p->stream); },
+                          [&] { return rh::launch_adjoint_x<T>(p->d.scheme, x, init, p->stream); },
                           "adjoint sweep launch");
-        if (st != RH_OK) return st;
-        if ((st = tr(bT, out, n[0], n[1], init, s)) != RH_OK) return st;
     } else if (init.X1 || init.X2 || init.X3) {
         st = timed_launch(p, RH_KERNEL_OTHER, [&] {
             return rh::launch_lincomb<T>(out, N, init.a1, init.X1, init.a2, init.X2, init.a3, init.X3, (T)0,
                                          nullptr, p->stream);
         }, "combine launch");
-        if (st != RH_OK) return st;
     } else {
         st = timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_fill_zero<T>(out, N, p->stream); },
                           "fill launch");
-        if (st != RH_OK) return st;
     }
-    // the y and z sweeps read the recovery and its derivatives from a six-field
-    // pack in the workspace (the transposed copies are no longer needed)
-    T* pk = (T*)p->ws;
-    if (n[1] > 1 || n[2] > 1) {
-        st = timed_launch(p, RH_KERNEL_OTHER,
-                          [&] { return rh::launch_adjoint_pack<T>(u, pk, p->ncell, p->stream); }, "pack launch");
-        if (st != RH_OK) return st;
-    }
+    if (st != RH_OK) return st;
     for (int d = 1; d < 3; ++d) {
         if (n[d] < 2) continue;   // a one-cell axis contributes nothing to L
         rh::AdjArgs<T> q = base;
-        q.pk = pk;
-        q.u = u;
-        q.w = w;
-        q.ub = out;
-        q.n[0] = n[0];
-        q.n[1] = n[1];
-        q.n[2] = n[2];
         q.bc = p->d.bc[d];
         q.inv_h = (T)(1.0 / h[d]);
-        q.scale = s;
-        q.hb.c0[0] = p->d.x0;
-        q.hb.c0[1] = p->d.y0;
-        q.hb.c0[2] = p->d.z0;
-        q.hb.h[0] = h[0];
-        q.hb.h[1] = h[1];
-        q.hb.h[2] = h[2];
         st = timed_launch(p, RH_KERNEL_ADJOINT,
                           [&] { return rh::launch_adjoint_sweep<T>(d, p->d.scheme, q, p->stream); },
                           "adjoint sweep launch");

@@ -67,30 +67,28 @@ struct AdjArgs {
     T eps;
     T scale;            // ub += scale * (J^T w) of this axis
     const T* pk;        // per-cell recovery pack (kappa, p, dkappa/dE, dkappa/dM2, dp/dE, dp/dM2) or null
-    int zero_init;      // ub starts at zero: the first pass writes it without reading
     HubbleBC hb;
 };
 
-// dir is 1 (y) or 2 (z); the x axis runs as a y sweep on x-y transposed copies.
-// With a.pk set the sweep reads the recovery and its derivatives from the pack
-// instead of recomputing them.
+// y (dir 1) or z (dir 2) axis of the adjoint: a.ub += a.scale J_dir^T w.
+// a.pk (required) holds the recovery and its derivatives for every cell.
 template <class T>
 hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s);
 // Fill the six-field recovery pack of state u (layout [5][ncell] -> [6][ncell]).
 template <class T>
 hipError_t launch_adjoint_pack(const T* u, T* pk, long long ncell, hipStream_t s);
-// Per z-plane transpose of a [5][nz][R][C] field set into [5][nz][C][R] with the
-// two in-plane momentum fields (1 and 2) exchanged:
-//   out = a1 X1 + a2 X2 + a3 X3 + s transpose(in)   (null X terms are skipped).
-// X1..X3 have the output layout and may alias out.
+
+// Linear combination a1 X1 + a2 X2 + a3 X3 of state-layout buffers (null X
+// terms are skipped; they may alias the output).
 template <class T>
 struct Lin3 {
     T a1, a2, a3;
     const T *X1, *X2, *X3;
 };
+// x axis of the adjoint (LDS tiles): a.ub = init + a.scale J_x^T w, written
+// without reading a.ub.  a.pk (required) holds the recovery pack.
 template <class T>
-hipError_t launch_transpose_xy(const T* in, T* out, int R, int C, int nz, long long fstride, Lin3<T> init, T s,
-                               hipStream_t st);
+hipError_t launch_adjoint_x(int order, AdjArgs<T> a, Lin3<T> init, hipStream_t s);
 template <class T>
 hipError_t launch_fill_zero(T* p, long long n, hipStream_t s);
 template <class T>
