@@ -4,7 +4,8 @@ times (the library's default tile and segment choice for the shape).
 * the 256^3 ellipsoidal blob (WENO5 and WENO7, FP64 and FP32): one SSP-RK3 step,
   every cell of every field against the FP64 oracle's step;
 * the 128^3 Hubble-like flow on [-5, 5]^3 with analytic ghosts: ten steps, FP64
-  and FP32, against the oracle;
+  and FP32, against the oracle, and the whole 100-step run (FP64 against the
+  oracle, FP32 against FP64, the energy density against its closed form);
 * the 64-event hot-spot ensemble advanced as one batch: the smallest and the
   largest events against the oracle run of the same event alone.
 
@@ -86,3 +87,33 @@ def test_ensemble_events_against_oracle():
         err = field_errors(got[g], ref)
         print(g, sizes[g], err, flush=True)
         assert np.all(err <= 2e-5), (g, err)
+
+
+def test_hubble_128_full_run_against_analytic():
+    """The whole Hubble-like run: 128^3 on [-5, 5]^3, WENO5, 100 steps to t = 13.125.
+    FP64 on the GPU equals the FP64 oracle (1e-12 per field); FP32 stays within
+    1e-5 of FP64 per field; the energy density matches the closed form e(tau) to
+    the same (discretisation) error as the oracle's."""
+    rh = rh_module()
+    spec = inputs.hubble(n=128, order=5)
+    g64, t, _, cnt = gpu_steps(spec, rh.RH_PREC_FP64, 100)
+    g32, _, _, cnt32 = gpu_steps(spec, rh.RH_PREC_FP32, 100)
+    assert t == pytest.approx(13.125, abs=1e-12)
+    assert cnt == [0, 0] and cnt32[1] == 0
+    ref, _ = oracle_steps(spec, 100)
+    err64 = field_errors(g64, ref)
+    err32 = field_errors(g32, g64)
+    n = spec["shape"][0]
+    ax = spec["c0"][0] + spec["h"][0] * np.arange(n)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    exact_e = oracle.hubble_prim(spec["hub"], t, xyz)[0].reshape(n, n, n)
+    inner = (slice(8, -8),) * 3   # away from the analytic boundary cells
+    e_gpu = oracle.con2prim(g64)[0]
+    e_orc = oracle.con2prim(ref)[0]
+    rel = lambda e: np.abs(e[inner] - exact_e[inner]).max() / np.abs(exact_e[inner]).max()
+    print("fp64 vs oracle", err64, "fp32 vs fp64", err32, "e vs closed form: gpu %.3e oracle %.3e"
+          % (rel(e_gpu), rel(e_orc)), flush=True)
+    assert np.all(err64 <= 1e-12), err64
+    assert np.all(err32 <= 1e-5), err32
+    assert abs(rel(e_gpu) - rel(e_orc)) <= 1e-9 * max(1.0, rel(e_orc))
