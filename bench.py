@@ -155,6 +155,48 @@ def run_adjoint(spec, precision, reps):
             "adjoint_sweeps_ms_per_step_vjp": kt["adjoint"][0] / reps}
 
 
+def run_diff(n_steps=50, every=10):
+    """The differentiable run: one 96^3 hot-spot event (FP32, WENO5), 50 steps with
+    a checkpoint every 10, the anisotropy loss and its gradient with respect to the
+    initial energy density through the autograd function.  Reports the forward
+    time, the backward time (replays plus adjoint steps) and the adjoint of one
+    step from stored stages against one forward step on this grid."""
+    import torch
+    from paper_1604_03360_amd import autograd, inputs, rh
+    spec = inputs.diff_event(n=96)
+    adj = run_adjoint(spec, "fp32", 10)
+    h = rh.Hydro.from_spec(spec, precision=rh.RH_PREC_FP32)
+    e0 = torch.tensor(spec["prim"][0], dtype=torch.float64, device="cuda").requires_grad_(True)
+    z = torch.zeros_like(e0)
+
+    def loss_and_grad():
+        u0 = torch.stack([e0, z, z, z, e0 ** 0.75]).to(torch.float32)
+        h.t = 0.0
+        t0 = time.perf_counter()
+        uT = autograd.run(u0, h, spec["dt"], n_steps, every)
+        uT = uT.double()
+        loss = (uT[1] ** 2 - uT[2] ** 2).sum() / uT[0].sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e0.grad = None
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    loss_and_grad()                    # warm-up
+    fwd_s, bwd_s = loss_and_grad()
+    h.close()
+    del h, e0
+    torch.cuda.empty_cache()
+    return {"grid": [96, 96, 96], "steps": n_steps, "checkpoint_every": every,
+            "forward_s": fwd_s, "backward_s": bwd_s, "backward_over_forward": bwd_s / fwd_s,
+            "adjoint_step_ratio": adj["ratio"], "adjoint_step_ratio_with_recompute": adj["ratio_with_recompute"],
+            "step_vjp_ms": adj["step_vjp_ms"], "step_ms": adj["step_ms"],
+            "workload": "one 96^3 hot-spot event, FP32, WENO5, dt=0.06, gradient of sum(Mx^2-My^2)/sum(E) "
+                        "at the final time with respect to the initial e"}
+
+
 def run_batch(steps, warmup):
     """The 64-event hot-spot ensemble (FP32, WENO5): autotuned launch shapes,
     graph-captured steps; events resident in HBM before the timed region."""
@@ -277,6 +319,11 @@ def main():
         print("bench: adjoint step %.3f ms (%.3f ms with recomputation) vs forward step %.3f ms "
               "(ratio %.2f, %.2f)" % (adj["step_vjp_ms"], adj["step_vjp_recompute_ms"], adj["step_ms"],
                                       adj["ratio"], adj["ratio_with_recompute"]), file=sys.stderr, flush=True)
+    diff = None
+    if not args.no_adjoint:
+        diff = run_diff()
+        print("bench: 96^3 differentiable run: forward %.3f s, backward %.3f s; adjoint step ratio %.2f"
+              % (diff["forward_s"], diff["backward_s"], diff["adjoint_step_ratio"]), file=sys.stderr, flush=True)
     bat = None
     if not args.no_batch:
         bat = run_batch(min(args.steps, 10), 2)
@@ -301,6 +348,8 @@ def main():
         out["adjoint"] = dict(adj, workload="same grid, FP32: adjoint of one SSP-RK3 step with its "
                                            "stage states resident / one forward step; with the stage "
                                            "states recomputed in ratio_with_recompute")
+    if diff is not None:
+        out["differentiable_run"] = diff
     if bat is not None:
         out["batch"] = bat
     if r64 is not None:
