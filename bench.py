@@ -270,10 +270,26 @@ def cpu_baseline(spec, nsteps):
     oracle.step(g, u, spec["dt"], nsteps)
     el = time.perf_counter() - t0
     ncell = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
-    return {"value": ncell * nsteps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d whole-grid SSP-RK3 step(s) of the same 256^3 WENO5 blob, FP64, %.1f s"
-                      % (nsteps, el)}
+    cores = oracle.num_threads()
+    out = {"value": ncell * nsteps / el, "unit": "cell-updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "%d whole-grid SSP-RK3 step(s) of the same %d^3 WENO%d blob, FP64, %.1f s"
+                     % (nsteps, spec["shape"][0], spec["order"], el)}
+    # single-threaded, as the paper's CPU comparison: one step of the blob at 96^3
+    from paper_1604_03360_amd import inputs
+    small = inputs.blob(n=96, order=spec["order"])
+    g1 = oracle.grid_from_spec(small)
+    u1 = oracle.prim2con(small["prim"])
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(g1, u1, small["dt"], 1)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    out["single_thread"] = {"value": 96 ** 3 / el1, "unit": "cell-updates/s", "cores": 1,
+                            "sample": "1 SSP-RK3 step of the blob at 96^3 (dx 0.1), FP64, %.1f s" % el1}
+    return out
 
 
 def main():

@@ -67,6 +67,8 @@ def lib():
         L.orc_jvp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
         L.orc_riemann_conformal.argtypes = [ctypes.c_double] * 4 + [ctypes.c_long, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_vjp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
         L.orc_vjp_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.orc_jvp_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
@@ -77,6 +79,11 @@ def lib():
 def num_threads():
     """Threads the oracle's OpenMP loops use."""
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    """Set the threads of the oracle's OpenMP loops (for timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def _dp(a):

@@ -550,6 +550,16 @@ int orc_riemann_conformal(double eL, double nL, double eR, double nR, long n, co
 #include <omp.h>
 #endif
 
+// Thread count of the OpenMP loops over grid lines (n >= 1); used only to time
+// the oracle single-threaded.
+extern "C" void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 extern "C" int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
