@@ -76,6 +76,7 @@ def run_gpu(spec, precision, steps, warmup):
     prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
     h = rh.Hydro.from_spec(spec, precision=prec)
     h.set_primitive(spec["prim"])
+    rh.rh_set_graph(h.plan, 1)   # steps replayed from one captured graph
     dt = spec["dt"]
     if warmup:
         h.step(dt, warmup)

@@ -153,6 +153,14 @@ rh_status rh_step(rh_plan* plan, double dt, int n_steps, double* t_inout);
  * stream.  Errors: RH_E_STATE, RH_E_HIP, RH_E_PHYS (strict plans only). */
 rh_status rh_totals(rh_plan* plan, double out[5], long long counters[2]);
 
+/* Replay steps from a graph (enable != 0): rh_step then captures one SSP-RK3
+ * step (its sweep launches, Sec. 1) into a hipGraph on first use and launches
+ * that graph once per step; the graph is rebuilt when dt or the bound buffers
+ * change.  Results are bitwise those of eager launches.  Plans with an analytic
+ * boundary, and steps taken while per-launch timing is on, run eagerly.
+ * Errors: RH_E_INVAL (NULL plan). */
+rh_status rh_set_graph(rh_plan* plan, int enable);
+
 /* Reset the floor counter reported by rh_totals to zero (asynchronous). */
 rh_status rh_reset_counters(rh_plan* plan);
 

@@ -53,6 +53,14 @@ struct rh_plan {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
+    // one captured step, replayed by rh_step when enabled
+    bool graph_on = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_dt = 0.0;
+    const void* graph_state = nullptr;
+    const void* graph_ws = nullptr;
 };
 
 namespace {
@@ -128,10 +136,10 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
     for (int d = 0; d < 3; ++d)
         if (n[d] > 1) active[na++] = d;
     if (na == 0) {
-        if (stage == rh::STAGE_WRITE_L) {
-            hipError_t e = hipMemsetAsync(lacc, 0, 5 * p->ncell * sizeof(T), p->stream);
-            return e == hipSuccess ? RH_OK : hip_fail(e, "hipMemsetAsync");
-        }
+        if (stage == rh::STAGE_WRITE_L)
+            return timed_launch(p, RH_KERNEL_OTHER,
+                                [&] { return rh::launch_fill_zero<T>(lacc, 5 * p->ncell, p->stream); },
+                                "fill launch");
         return timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_combine<T>(a, p->stream); },
                             "combine launch");
     }
@@ -151,21 +159,75 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
 }
 
 template <class T>
-rh_status step_impl(rh_plan* p, double dt, int nsteps, double t, T* stages = nullptr) {
+rh_status one_step(rh_plan* p, double dt, double t, T* stages) {
     const size_t S = 5 * (size_t)p->ncell;
     T* U0 = (T*)p->state;
     T* U1 = stages ? stages : (T*)p->ws;   // stage states go to the caller's store if given
     T* U2 = U1 + S;
     T* Lc = (T*)p->ws + 2 * S;
-    for (int s = 0; s < nsteps; ++s) {
-        rh_status st;
-        st = evaluate<T>(p, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
-        if (st != RH_OK) return st;
-        st = evaluate<T>(p, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2);
-        if (st != RH_OK) return st;
-        st = evaluate<T>(p, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3);
-        if (st != RH_OK) return st;
-        t += dt;
+    rh_status st = evaluate<T>(p, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
+    if (st == RH_OK) st = evaluate<T>(p, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2);
+    if (st == RH_OK) st = evaluate<T>(p, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3);
+    return st;
+}
+
+void drop_graph(rh_plan* p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+}
+
+bool any_hubble(const rh_plan* p) {
+    return p->d.bc[0] == RH_BC_HUBBLE || p->d.bc[1] == RH_BC_HUBBLE || p->d.bc[2] == RH_BC_HUBBLE;
+}
+
+// n steps: eager launches, or replays of one captured step when graphs are on
+// (not with analytic boundaries, whose stage times change every step, and not
+// while per-launch timing is on)
+template <class T>
+rh_status step_impl(rh_plan* p, double dt, int nsteps, double t, T* stages = nullptr) {
+    const bool use_graph = p->graph_on && !stages && !any_hubble(p) && !p->timing;
+    if (!use_graph) {
+        for (int s = 0; s < nsteps; ++s) {
+            rh_status st = one_step<T>(p, dt, t, stages);
+            if (st != RH_OK) return st;
+            t += dt;
+        }
+        return RH_OK;
+    }
+    if (nsteps == 0) return RH_OK;
+    if (!p->graph_exec || p->graph_dt != dt || p->graph_state != p->state || p->graph_ws != p->ws) {
+        drop_graph(p);
+        hipError_t e;
+        if (!p->cap_stream &&
+            (e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        hipStream_t keep = p->stream;
+        p->stream = p->cap_stream;
+        rh_status st = one_step<T>(p, dt, t, nullptr);
+        p->stream = keep;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->cap_stream, &g);
+        if (st != RH_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        p->graph = g;
+        if ((e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            drop_graph(p);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        p->graph_dt = dt;
+        p->graph_state = p->state;
+        p->graph_ws = p->ws;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        hipError_t e = hipGraphLaunch(p->graph_exec, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
     return RH_OK;
 }
@@ -236,6 +298,9 @@ rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* d) {
 
 void rh_plan_destroy(rh_plan* p) {
     if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    drop_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->d_clamps) (void)hipFree(p->d_clamps);
     if (p->d_partials) (void)hipFree(p->d_partials);
     if (p->d_totals) (void)hipFree(p->d_totals);
@@ -310,6 +375,13 @@ rh_status rh_step(rh_plan* p, double dt, int n_steps, double* t_inout) {
                     : step_impl<double>(p, dt, n_steps, *t_inout);
     if (st == RH_OK) *t_inout += n_steps * dt;
     return st;
+}
+
+rh_status rh_set_graph(rh_plan* p, int enable) {
+    if (!p) return fail(RH_E_INVAL, "plan is NULL");
+    p->graph_on = enable != 0;
+    if (!p->graph_on) drop_graph(p);
+    return RH_OK;
 }
 
 rh_status rh_totals(rh_plan* p, double out[5], long long counters[2]) {

@@ -75,6 +75,7 @@ def library():
         L.rh_vjp_workspace_bytes.restype = ctypes.c_size_t
         L.rh_step_vjp.argtypes = [vp, d, d, vp, vp, vp, vp]
         L.rh_step_store.argtypes = [vp, d, ctypes.POINTER(d), vp]
+        L.rh_set_graph.argtypes = [vp, i]
         L.rh_step_vjp_stored.argtypes = [vp, d, d, vp, vp, vp, vp, vp]
         llp = ctypes.POINTER(ctypes.c_longlong)
         ip = ctypes.POINTER(ctypes.c_int)
@@ -191,6 +192,10 @@ def rh_step_vjp(plan, t, dt, un_ptr, bin_ptr, bout_ptr, scratch_ptr):
     _check(library().rh_step_vjp(plan, float(t), float(dt), ctypes.c_void_p(un_ptr),
                                  ctypes.c_void_p(bin_ptr), ctypes.c_void_p(bout_ptr),
                                  ctypes.c_void_p(scratch_ptr)))
+
+
+def rh_set_graph(plan, enable):
+    _check(library().rh_set_graph(plan, 1 if enable else 0))
 
 
 def rh_step_store(plan, dt, t, stages_ptr):
