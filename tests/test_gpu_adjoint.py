@@ -16,6 +16,12 @@ CASES = {
     "hubble": lambda o: inputs.hubble(n=20, order=o, half_width=3.0),
     "hotspots": lambda o: inputs.hotspots(9, size=32, order=o),
     "tiny_periodic": lambda o: inputs.random_smooth((6, 5, 4), h=0.2, seed=63, order=o),
+    # degenerate axes: a line along x, planes without x and without y
+    "line_x_outflow": lambda o: inputs.random_smooth((90, 1, 1), h=0.05, seed=64, order=o,
+                                                     bc=(inputs.BC_OUTFLOW,) * 3),
+    "plane_yz": lambda o: inputs.random_smooth((1, 27, 21), h=0.1, seed=65, order=o),
+    "plane_xz_outflow": lambda o: inputs.random_smooth((35, 1, 18), h=0.1, seed=66, order=o,
+                                                       bc=(inputs.BC_OUTFLOW,) * 3),
 }
 
 
@@ -63,7 +69,8 @@ def test_vjp_L_dot_product_with_oracle_jvp(order):
 
 
 @pytest.mark.parametrize("order", [5, 7])
-@pytest.mark.parametrize("case", ["smooth_periodic", "smooth_outflow", "hubble", "hotspots"])
+@pytest.mark.parametrize("case", ["smooth_periodic", "smooth_outflow", "hubble", "hotspots", "line_x_outflow",
+                                  "plane_yz"])
 def test_step_vjp_fp64_matches_oracle(case, order):
     rh = rh_module()
     spec = CASES[case](order)
