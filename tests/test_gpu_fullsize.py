@@ -7,7 +7,8 @@ times (the library's default tile and segment choice for the shape).
   and FP32, against the oracle, and the whole 100-step run (FP64 against the
   oracle, FP32 against FP64, the energy density against its closed form);
 * the 64-event hot-spot ensemble advanced as one batch: the smallest and the
-  largest events against the oracle run of the same event alone.
+  largest events against the oracle run of the same event alone;
+* the blob's full run length (200 steps) on a 64^3 variant.
 
 Bars as in the small-grid parity tests: 1e-12 (FP64) and 2e-5 (FP32) normalised
 L-infinity per field.
@@ -117,3 +118,19 @@ def test_hubble_128_full_run_against_analytic():
     assert np.all(err64 <= 1e-12), err64
     assert np.all(err32 <= 1e-5), err32
     assert abs(rel(e_gpu) - rel(e_orc)) <= 1e-9 * max(1.0, rel(e_orc))
+
+
+def test_blob_64_full_length():
+    """The blob's full run length (200 steps of dt = 0.04 to t = 8) on a 64^3 variant
+    (dx = 0.1, periodic): FP64 against the oracle step for step, FP32 against FP64."""
+    rh = rh_module()
+    spec = inputs.blob(n=64, order=5)
+    g64, _, tot, cnt = gpu_steps(spec, rh.RH_PREC_FP64, 200)
+    g32, _, _, cnt32 = gpu_steps(spec, rh.RH_PREC_FP32, 200)
+    ref, _ = oracle_steps(spec, 200)
+    err64 = field_errors(g64, ref)
+    err32 = field_errors(g32, g64)
+    print("blob 64^3 x 200: fp64 vs oracle", err64, "fp32 vs fp64", err32, flush=True)
+    assert np.all(err64 <= 1e-12), err64
+    assert np.all(err32 <= 1e-4), err32
+    assert cnt == [0, 0] and cnt32[1] == 0
