@@ -18,8 +18,8 @@
  *     caller owns every buffer passed in (the library never frees them).
  *   - All work is enqueued asynchronously on the stream given to rh_bind
  *     (a hipStream_t passed as void*; NULL means the legacy default stream).
- *     Only rh_totals, rh_kernel_times and the *_fields calls with a host
- *     result synchronise that stream.
+ *     Only rh_totals, rh_kernel_times, rh_plan_destroy and the batch calls
+ *     that return host data synchronise that stream.
  *   - Every call returns RH_OK (0) or a negative rh_status; the message of
  *     the last failure on the calling thread is available from rh_last_error.
  *     No C++ exception crosses this interface.
@@ -98,8 +98,8 @@ const char* rh_version(void);
  * Errors: RH_E_INVAL (bad description), RH_E_NOMEM, RH_E_HIP. */
 rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* desc);
 
-/* Release a plan and its own device memory; never touches caller buffers.
- * The caller must ensure no work of this plan is still running. NULL is ignored. */
+/* Release a plan and its own device memory (after waiting for the plan's work
+ * on its bound stream); never touches caller buffers.  NULL is ignored. */
 void rh_plan_destroy(rh_plan* plan);
 
 /* Bytes of one state: 5 * nx * ny * nz * (8 for FP64, 4 for FP32). */
