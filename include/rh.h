@@ -93,8 +93,9 @@ const char* rh_last_error(void);
 const char* rh_version(void);
 
 /* Create a plan for one grid (Eq. (2) on a Cartesian grid).  Validates the
- * description and allocates only small plan-owned device memory (counters and
- * reduction partials).  *out receives the plan; it is NULL on failure.
+ * description (axes of 1 .. 2^24 cells, one field below 4 GiB) and allocates
+ * only small plan-owned device memory (counters and reduction partials).  *out
+ * receives the plan; it is NULL on failure.
  * Errors: RH_E_INVAL (bad description), RH_E_NOMEM, RH_E_HIP. */
 rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* desc);
 

@@ -274,6 +274,9 @@ rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* d) {
         if (d->bc[a] == RH_BC_HUBBLE && !(d->hubble_t0 > 0.0))
             return fail(RH_E_INVAL, "HUBBLE boundaries need hubble_t0 > 0");
     }
+    // the sweeps address one field with 32-bit byte offsets
+    const long long field_bytes = (long long)n[0] * n[1] * n[2] * (d->precision == RH_PREC_FP32 ? 4 : 8);
+    if (field_bytes >= (1LL << 32)) return fail(RH_E_INVAL, "one field must be smaller than 4 GiB");
     rh_plan* p = new (std::nothrow) rh_plan();
     if (!p) return fail(RH_E_NOMEM, "host allocation failed");
     p->d = *d;

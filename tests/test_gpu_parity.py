@@ -180,6 +180,17 @@ def test_zero_steps_and_errors():
     assert e.value.status == rh.RH_E_STATE
     rh.rh_plan_destroy(plan)
     h.close()
+    # plans whose fields would not be addressable, or with bad descriptions
+    for shape, prec in [((1024, 1024, 1024), rh.RH_PREC_FP32), ((1024, 1024, 600), rh.RH_PREC_FP64),
+                        ((0, 4, 4), rh.RH_PREC_FP32), ((1 << 25, 1, 1), rh.RH_PREC_FP32)]:
+        d = rh.make_desc(shape, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), 5, prec)
+        with pytest.raises(rh.RHError) as e:
+            rh.rh_plan_create(d)
+        assert e.value.status == rh.RH_E_INVAL, shape
+    d = rh.make_desc((16, 16, 16), (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), 6, rh.RH_PREC_FP32)
+    with pytest.raises(rh.RHError) as e:
+        rh.rh_plan_create(d)
+    assert e.value.status == rh.RH_E_INVAL
 
 
 def test_strict_mode_reports_floors():
