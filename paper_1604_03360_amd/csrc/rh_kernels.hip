@@ -52,6 +52,27 @@ __device__ __forceinline__ void load_cell(const SweepArgs<T>& A, int ix, int iy,
     for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
 }
 
+// State of cell x of grid row `row` (row = y + ny z), ghosts along x by the
+// boundary condition; the row is split into (y, z) only for analytic ghosts.
+template <class T>
+__device__ __forceinline__ void load_cell_x(const SweepArgs<T>& A, int x, int row, T u[5]) {
+    const int nx = A.n[0];
+    if (x < 0 || x >= nx) {
+        if (A.bc == RH_BC_PERIODIC) {
+            x %= nx;
+            if (x < 0) x += nx;
+        } else if (A.bc == RH_BC_OUTFLOW) {
+            x = x < 0 ? 0 : nx - 1;
+        } else {
+            load_cell<T, 0>(A, x, row % A.n[1], row / A.n[1], u);
+            return;
+        }
+    }
+    const long long id = x + (long long)nx * row;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = A.us[f * A.fstride + id];
+}
+
 // One reconstruction from a window of 2R split fluxes of cells i-R+1 .. i+R
 // (interface i+1/2): plus = left-biased on f+, minus = mirrored on f-.
 // WENO5 takes 4 eps (its smoothness indicators are carried as 4 beta).
@@ -112,7 +133,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
         const int row = r0 + ly, gx = x0 + lx - G;
         if (row < nrows && gx < nx + G) {
             T u[5], fp[5], fm[5];
-            load_cell<T, 0>(A, gx, row % ny, row / ny, u);
+            load_cell_x<T>(A, gx, row, u);
             split_flux<T, 0>(u, fp, fm, clamped);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
