@@ -114,30 +114,32 @@ __device__ __forceinline__ void split_flux(const T u[5], T fp[5], T fm[5], unsig
 // Written in the differences E_j = s_j - s_{j-1} about the centre c = s2:
 //   q_k - c:  (-E1/3 + 5 E2/6), (E2/6 + E3/3), (2 E3/3 - E4/6)
 //   beta_k = 13/12 A_k^2 + 1/4 B_k^2 with A = (E2-E1, E3-E2, E4-E3),
-//            B = (3E2-E1, E2+E3, E4-3E3);
-// 4 beta_k = 13/3 A^2 + B^2 is used with 4 eps (the common factor cancels), and
-// alpha_k = d_k / (eps + beta_k)^2 is evaluated with one reciprocal as
-// d_k prod_{j != k} g_j / sum(...), g_j = (4 eps + 4 beta_j)^2, d = (1, 6, 3)/10.
+//            B = (3E2-E1, E2+E3, E4-3E3).
+// Expanded in the E's, 4 beta_k = 16/3 h_k with
+//   h0 = E1^2 - 11/4 E1 E2 + 5/2 E2^2,  h1 = E2^2 - 5/4 E2 E3 + E3^2,
+//   h2 = E4^2 - 11/4 E3 E4 + 5/2 E3^2
+// (positive definite), so g_k = (h_k + 3/16 (4 eps))^2 is (3/16)^2 (4 eps +
+// 4 beta_k)^2 and the common factor cancels in the weights
+// alpha_k = d_k / (eps + beta_k)^2, d = (1, 6, 3)/10, which are evaluated with
+// one reciprocal and carried as 10 w = (g1 g2, 6 g0 g2, 3 g0 g1), the factors 6
+// and 3 folded into the candidates of the numerator:
+//   num = g2 (g1 dq0 + g0 (6 dq1)) + g0 g1 (3 dq2),  den = g2 (g1 + 6 g0) + 3 g0 g1.
 template <class T>
 __device__ __forceinline__ T weno5(T s0, T s1, T s2, T s3, T s4, T eps4) {
     const T E1 = s1 - s0, E2 = s2 - s1, E3 = s3 - s2, E4 = s4 - s3;
-    const T dq0 = (T)(5.0 / 6.0) * E2 - (T)(1.0 / 3.0) * E1;
-    const T dq1 = (T)(1.0 / 6.0) * E2 + (T)(1.0 / 3.0) * E3;
-    const T dq2 = (T)(2.0 / 3.0) * E3 - (T)(1.0 / 6.0) * E4;
-    const T A0 = E2 - E1, A1 = E3 - E2, A2 = E4 - E3;
-    const T B0 = (T)3 * E2 - E1, B1 = E2 + E3, B2 = E4 - (T)3 * E3;
-    const T c133 = (T)(13.0 / 3.0);
-    T g0 = (c133 * A0) * A0 + (B0 * B0 + eps4);
-    T g1 = (c133 * A1) * A1 + (B1 * B1 + eps4);
-    T g2 = (c133 * A2) * A2 + (B2 * B2 + eps4);
+    const T dq0 = (T)(5.0 / 6.0) * E2 - (T)(1.0 / 3.0) * E1;   // q0 - c
+    const T dq1s = E2 + (T)2 * E3;                              // 6 (q1 - c)
+    const T dq2s = (T)2 * E3 - (T)0.5 * E4;                     // 3 (q2 - c)
+    const T e = (T)0.1875 * eps4;
+    T g0 = E1 * (E1 - (T)2.75 * E2) + ((T)2.5 * E2 * E2 + e);
+    T g1 = E2 * (E2 - (T)1.25 * E3) + (E3 * E3 + e);
+    T g2 = E4 * (E4 - (T)2.75 * E3) + ((T)2.5 * E3 * E3 + e);
     g0 *= g0;
     g1 *= g1;
     g2 *= g2;
-    // w0 = 0.1 g1 g2, w1 = 0.6 g0 g2, w2 = 0.3 g0 g1, factored through g2
-    const T e0 = (T)0.1 * g1, e1 = (T)0.6 * g0;
-    const T P = (T)0.5 * (e1 * g1);
-    const T num = g2 * (e0 * dq0 + e1 * dq1) + P * dq2;
-    const T den = g2 * (e0 + e1) + P;
+    const T a = g0 * g1;
+    const T num = g2 * (g1 * dq0 + g0 * dq1s) + a * dq2s;
+    const T den = g2 * ((T)6 * g0 + g1) + (T)3 * a;
     return s2 + num * fast_rcp(den);
 }
 
