@@ -86,10 +86,15 @@ __device__ __forceinline__ void recover_vp(double E, double Mx, double My, doubl
 }
 
 // Split fluxes f+- = (F_d(u) +- u) / 2 of one cell along axis DIR, given the
-// velocity along DIR and the pressure.
+// velocity along DIR and the pressure, returned doubled (F_d +- u).
+//
+// The forward sweeps work with twice the split fluxes, F +- u: the WENO
+// reconstruction is homogeneous of degree one when eps scales with the square
+// of the data, so reconstructing F +- u with 4 eps gives exactly (all scalings
+// are powers of two) twice the face flux, and the factor 1/2 is folded into
+// the flux difference.
 template <class T, int DIR>
 __device__ __forceinline__ void split_flux_vp(const T u[5], T v, T P, T fp[5], T fm[5]) {
-    const T half = (T)0.5;
     T f[5];
     f[0] = u[1 + DIR];
     f[1] = u[1] * v + (DIR == 0 ? P : (T)0);
@@ -98,8 +103,8 @@ __device__ __forceinline__ void split_flux_vp(const T u[5], T v, T P, T fp[5], T
     f[4] = u[4] * v;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        fp[c] = half * (f[c] + u[c]);
-        fm[c] = half * (f[c] - u[c]);
+        fp[c] = f[c] + u[c];
+        fm[c] = f[c] - u[c];
     }
 }
 

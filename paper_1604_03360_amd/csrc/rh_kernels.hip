@@ -147,12 +147,13 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, row = r0 + ly;
     const bool active = gx < nx && row < nrows;
+    const T eps2 = (T)4 * A.eps;   // the staged split fluxes are doubled
     T Fr[5];
     if (active) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             const int o = (c * TY + ly) * PW + lx + 1;
-            Fr[c] = recon_plus<T, ORDER>(sp + o, A.eps) + recon_minus<T, ORDER>(sm + o, A.eps);
+            Fr[c] = recon_plus<T, ORDER>(sp + o, eps2) + recon_minus<T, ORDER>(sm + o, eps2);
         }
     }
     // left face of the tile's first column, one reconstruction per lane:
@@ -163,7 +164,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
         const int ely = tid / 10, ec = (tid % 10) >> 1, esg = tid & 1;
         if (r0 + ely < nrows) {
             const int o = (ec * TY + ely) * PW;   // window starts at staged column 0
-            ex = esg == 0 ? recon_plus<T, ORDER>(sp + o, A.eps) : recon_minus<T, ORDER>(sm + o, A.eps);
+            ex = esg == 0 ? recon_plus<T, ORDER>(sp + o, eps2) : recon_minus<T, ORDER>(sm + o, eps2);
         }
     }
     __syncthreads();
@@ -181,7 +182,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
         for (int c = 0; c < 5; ++c) {
             const T Fl = lx == 0 ? fe[ly * 10 + c * 2] + fe[ly * 10 + c * 2 + 1]
                                  : fh[(c * TY + ly) * (TX + 1) + lx];
-            L[c] = (Fl - Fr[c]) * A.inv_h;
+            L[c] = (Fl - Fr[c]) * ((T)0.5 * A.inv_h);
         }
         epilogue(A, gx + (long long)nx * row, L);
     }
@@ -248,10 +249,12 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
             wm[c][j] = fm[c];
         }
     }
+    const T eps2 = (T)4 * A.eps;   // the window holds doubled split fluxes
+    const T hinv = (T)0.5 * A.inv_h;
     T Fl[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c)
-        Fl[c] = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
+        Fl[c] = recon_plus<T, ORDER>(wp[c], eps2) + recon_minus<T, ORDER>(wm[c], eps2);
 
     T nxt[5];
     fetch(k0 + R, nxt);
@@ -288,8 +291,8 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
         T Lk[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            const T Fr = recon_plus<T, ORDER>(wp[c], A.eps) + recon_minus<T, ORDER>(wm[c], A.eps);
-            Lk[c] = (Fl[c] - Fr) * A.inv_h;
+            const T Fr = recon_plus<T, ORDER>(wp[c], eps2) + recon_minus<T, ORDER>(wm[c], eps2);
+            Lk[c] = (Fl[c] - Fr) * hinv;
             Fl[c] = Fr;
         }
         if constexpr (sizeof(T) != 4) load_epilogue();
