@@ -530,9 +530,9 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
             if ((periodic || (i >= -1 && i <= nx - 1)) && r0 + fy < nrows) {
                 const T g = (sw[c][fy][fl + 1] - sw[c][fy][fl]) * A.inv_h;
                 if constexpr (ORDER == 5) {
-                    weno5_grad_acc<T>(sfp[c][fy][fl], sfp[c][fy][fl + 1], sfp[c][fy][fl + 2], sfp[c][fy][fl + 3],
+                    weno5_grad_acc_e<T>(sfp[c][fy][fl], sfp[c][fy][fl + 1], sfp[c][fy][fl + 2], sfp[c][fy][fl + 3],
                                       sfp[c][fy][fl + 4], (T)4 * A.eps, g, op[0], op[1], op[2], op[3], op[4]);
-                    weno5_grad_acc<T>(sfm[c][fy][fl + 5], sfm[c][fy][fl + 4], sfm[c][fy][fl + 3],
+                    weno5_grad_acc_e<T>(sfm[c][fy][fl + 5], sfm[c][fy][fl + 4], sfm[c][fy][fl + 3],
                                       sfm[c][fy][fl + 2], sfm[c][fy][fl + 1], (T)4 * A.eps, g, om[4], om[3],
                                       om[2], om[1], om[0]);
                 } else {

@@ -58,6 +58,52 @@ __device__ __forceinline__ void weno5_grad_acc(T s0, T s1, T s2, T s3, T s4, T e
     o4 += gbar * d4;
 }
 
+// The same gradient written in the first differences E_j (the smoothness
+// indicators in the expanded form h_k of weno5): fewer instructions, more live
+// values; used where registers are plentiful (the LDS-tiled x adjoint).  With omega_k the
+// nonlinear weights, dq_k the candidates minus the centre and G_k = h_k + e:
+//   d fhat / d E_j = sum_k omega_k d dq_k/d E_j + sum_k c_k d h_k/d E_j,
+//   c_k = -2 omega_k (dq_k - sum_m omega_m dq_m) / G_k,
+// and d/d s follows from E_j = s_j - s_{j-1} (plus 1 on the centre s2).
+template <class T>
+__device__ __forceinline__ void weno5_grad_acc_e(T s0, T s1, T s2, T s3, T s4, T eps4, T gbar,
+                                                 T& o0, T& o1, T& o2, T& o3, T& o4) {
+    const T E1 = s1 - s0, E2 = s2 - s1, E3 = s3 - s2, E4 = s4 - s3;
+    const T dq0 = (T)(5.0 / 6.0) * E2 - (T)(1.0 / 3.0) * E1;
+    const T dq1 = (T)(1.0 / 6.0) * E2 + (T)(1.0 / 3.0) * E3;
+    const T dq2 = (T)(2.0 / 3.0) * E3 - (T)(1.0 / 6.0) * E4;
+    const T e = (T)0.1875 * eps4;
+    const T t0 = E1 - (T)2.75 * E2, t1 = E2 - (T)1.25 * E3, t2 = E4 - (T)2.75 * E3;
+    const T u0 = (T)2.5 * E2, u2 = (T)2.5 * E3;
+    const T G0 = E1 * t0 + (u0 * E2 + e);
+    const T G1 = E2 * t1 + (E3 * E3 + e);
+    const T G2 = E4 * t2 + (u2 * E3 + e);
+    const T g0 = G0 * G0, g1 = G1 * G1, g2 = G2 * G2;
+    // 10 w = (g1 g2, 6 g0 g2, 3 g0 g1)
+    const T p12 = g1 * g2, p02 = g0 * g2, p01 = g0 * g1;
+    const T rs = fast_rcp((T)3 * p01 + ((T)6 * p02 + p12));
+    const T om0 = p12 * rs, om1 = p02 * ((T)6 * rs), om2 = p01 * ((T)3 * rs);
+    const T fd = om0 * dq0 + om1 * dq1 + om2 * dq2;
+    const T gb2 = (T)(-2.0) * gbar;
+    const T c0 = (gb2 * om0) * (dq0 - fd) * fast_rcp(G0);
+    const T c1 = (gb2 * om1) * (dq1 - fd) * fast_rcp(G1);
+    const T c2 = (gb2 * om2) * (dq2 - fd) * fast_rcp(G2);
+    const T wb0 = gbar * om0, wb1 = gbar * om1, wb2 = gbar * om2;
+    // d h_k / d E_j
+    const T h0_1 = t0 + E1, h0_2 = (u0 + u0) - (T)2.75 * E1;
+    const T h1_2 = t1 + E2, h1_3 = (E3 + E3) - (T)1.25 * E2;
+    const T h2_3 = (u2 + u2) - (T)2.75 * E4, h2_4 = t2 + E4;
+    const T gE1 = c0 * h0_1 - (T)(1.0 / 3.0) * wb0;
+    const T gE2 = (c0 * h0_2 + c1 * h1_2) + ((T)(5.0 / 6.0) * wb0 + (T)(1.0 / 6.0) * wb1);
+    const T gE3 = (c1 * h1_3 + c2 * h2_3) + ((T)(1.0 / 3.0) * wb1 + (T)(2.0 / 3.0) * wb2);
+    const T gE4 = c2 * h2_4 - (T)(1.0 / 6.0) * wb2;
+    o0 -= gE1;
+    o1 += gE1 - gE2;
+    o2 += gbar + (gE2 - gE3);
+    o3 += gE3 - gE4;
+    o4 += gE4;
+}
+
 // Gradient of weno7 (see weno7) times gbar, added to o[0..6].  With
 // G_k = a1 (a1 + kk a3h) + a2h^2 + a3h^2 + eps (a2h = r2 a2, a3h = r3 a3,
 // kk = 1/(2 r3)):
