@@ -175,10 +175,29 @@ __device__ __forceinline__ T weno7(T s0, T s1, T s2, T s3, T s4, T s5, T s6, T e
     const T a3_1 = c6 * ((D2 + D4) - (T)2 * D3);
     const T a3_2 = c6 * ((D3 + D5) - (T)2 * D4);
     const T a3_3 = c6 * ((D4 + D6) - (T)2 * D5);
-    T g0 = a1_0 * (a1_0 + kk * a3_0) + (a2_0 * a2_0 + (a3_0 * a3_0 + eps));
-    T g1 = a1_1 * (a1_1 + kk * a3_1) + (a2_1 * a2_1 + (a3_1 * a3_1 + eps));
-    T g2 = a1_2 * (a1_2 + kk * a3_2) + (a2_1 * a2_1 + (a3_2 * a3_2 + eps));
-    T g3 = a1_3 * (a1_3 + kk * a3_3) + (a2_3 * a2_3 + (a3_3 * a3_3 + eps));
+    T g0, g1, g2, g3;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: 240 beta_k as quadratic forms in its three differences
+        // (x, y, z) = (D_{k+1}, D_{k+2}, D_{k+3}); the factor 240 (on eps too)
+        // cancels in the weights.  Fewer operations than the derivative form.
+        // Rounding in the terms grows by at most the ratio of the summed
+        // absolute coefficients to 240 (68 for the outer stencils): a few 1e-6
+        // relative in beta at FP32, far below the parity bar.
+        const T e = (T)240 * eps;
+        auto q = [e](T x, T y, T z, T cxx, T cxy, T cxz, T cyy, T cyz, T czz) {
+            return x * (cxx * x + cxy * y + cxz * z) + (y * (cyy * y + cyz * z) + (czz * z * z + e));
+        };
+        g0 = q(D1, D2, D3, (T)547, (T)-2788, (T)1854, (T)3708, (T)-5188, (T)2107);
+        g1 = q(D2, D3, D4, (T)267, (T)-1108, (T)494, (T)1468, (T)-1428, (T)547);
+        g2 = q(D3, D4, D5, (T)547, (T)-1428, (T)494, (T)1468, (T)-1108, (T)267);
+        g3 = q(D4, D5, D6, (T)2107, (T)-5188, (T)1854, (T)3708, (T)-2788, (T)547);
+    } else {
+        // FP64: the sum-of-squares form (no cancellation)
+        g0 = a1_0 * (a1_0 + kk * a3_0) + (a2_0 * a2_0 + (a3_0 * a3_0 + eps));
+        g1 = a1_1 * (a1_1 + kk * a3_1) + (a2_1 * a2_1 + (a3_1 * a3_1 + eps));
+        g2 = a1_2 * (a1_2 + kk * a3_2) + (a2_1 * a2_1 + (a3_2 * a3_2 + eps));
+        g3 = a1_3 * (a1_3 + kk * a3_3) + (a2_3 * a2_3 + (a3_3 * a3_3 + eps));
+    }
     g0 *= g0;
     g1 *= g1;
     g2 *= g2;
