@@ -22,38 +22,73 @@ namespace rh {
 
 namespace {
 
+// A field's base pointer made opaque once per lane-line: loads through it then
+// keep the scalar-base + 32-bit-offset form instead of being re-associated by
+// the compiler into per-lane 64-bit address arithmetic (one 64-bit add per
+// access).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> opaque_base(T* p) {
+    gptr<T> g = (gptr<T>)p;
+    asm("" : "+s"(g));
+    return g;
+}
+template <class T>
+__device__ __forceinline__ T ld_off(gptr<const T> base, uint32_t off) {
+    return *(gptr<const T>)((gptr<const char>)base + off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(gptr<T> base, uint32_t off, T v) {
+    *(gptr<T>)((gptr<char>)base + off) = v;
+}
+
 template <class T, int DIR>
 struct Column {
-    // lane -> line: plane axes are (y, z) for DIR 0, (x, z) for DIR 1, (x, y) for DIR 2
-    long long base;
-    long long stride;
+    gptr<const T> u[5];    // field base pointers (uniform)
+    gptr<const T> w[5];
+    gptr<const T> pk[6];
+    gptr<T> ub[5];
+    // lane -> line: plane axes are (y, z) for DIR 0, (x, z) for DIR 1, (x, y) for DIR 2;
+    // byte offsets of the line's first cell and between consecutive cells
+    uint32_t cb;
+    uint32_t sb;
     int ia, ib;   // the two transverse indices
 };
 
 template <class T, int DIR>
 __device__ __forceinline__ bool column_of(const AdjArgs<T>& A, unsigned p, Column<T, DIR>& C) {
     const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        C.u[f] = opaque_base(A.u + f * A.fstride);
+        C.w[f] = opaque_base(A.w + f * A.fstride);
+        C.ub[f] = opaque_base(A.ub + f * A.fstride);
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) C.pk[f] = opaque_base(A.pk + f * A.fstride);
     if (DIR == 0) {
         const int y = (int)(p % (unsigned)ny), z = (int)(p / (unsigned)ny);
         if (z >= nz) return false;
         C.ia = y;
         C.ib = z;
-        C.base = (long long)nx * (y + (long long)ny * z);
-        C.stride = 1;
+        C.cb = (uint32_t)sizeof(T) * ((uint32_t)nx * ((uint32_t)y + (uint32_t)ny * (uint32_t)z));
+        C.sb = (uint32_t)sizeof(T);
     } else if (DIR == 1) {
         const int x = (int)(p % (unsigned)nx), z = (int)(p / (unsigned)nx);
         if (z >= nz) return false;
         C.ia = x;
         C.ib = z;
-        C.base = x + (long long)nx * ny * z;
-        C.stride = nx;
+        C.cb = (uint32_t)sizeof(T) * ((uint32_t)x + (uint32_t)nx * (uint32_t)ny * (uint32_t)z);
+        C.sb = (uint32_t)sizeof(T) * (uint32_t)nx;
     } else {
         const int x = (int)(p % (unsigned)nx), y = (int)(p / (unsigned)nx);
         if (y >= ny) return false;
         C.ia = x;
         C.ib = y;
-        C.base = x + (long long)nx * y;
-        C.stride = (long long)nx * ny;
+        C.cb = (uint32_t)sizeof(T) * ((uint32_t)x + (uint32_t)nx * (uint32_t)y);
+        C.sb = (uint32_t)sizeof(T) * ((uint32_t)nx * (uint32_t)ny);
     }
     return true;
 }
@@ -87,15 +122,17 @@ __device__ __forceinline__ void adj_load(const AdjArgs<T>& A, const Column<T, DI
             return;
         }
     }
-    const long long id = C.base + mm * C.stride;
+    const uint32_t off = C.cb + (uint32_t)mm * C.sb;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
+    for (int f = 0; f < 5; ++f) u[f] = ld_off(C.u[f], off);
 }
 
 // State at line position m with its velocity along the sweep axis and pressure,
 // taken from the recovery pack (interior, periodic and outflow positions) or,
-// for analytic ghosts, evaluated and recovered here in FP64.
-template <class T, int DIR>
+// for analytic ghosts, evaluated and recovered here in FP64.  HUB = false
+// compiles the analytic branch out (its FP64 registers would otherwise count
+// against the whole rolling window).
+template <class T, int DIR, bool HUB>
 __device__ __forceinline__ void adj_state(const AdjArgs<T>& A, const Column<T, DIR>& C, int m, T u[5], T& v,
                                           T& P) {
     const int nd = A.n[DIR];
@@ -104,7 +141,7 @@ __device__ __forceinline__ void adj_state(const AdjArgs<T>& A, const Column<T, D
         if (A.bc == RH_BC_PERIODIC) {
             mm = m % nd;
             if (mm < 0) mm += nd;
-        } else if (A.bc == RH_BC_OUTFLOW) {
+        } else if (!HUB || A.bc == RH_BC_OUTFLOW) {
             mm = m < 0 ? 0 : nd - 1;
         } else {
             adj_load<T, DIR>(A, C, m, u);
@@ -116,11 +153,11 @@ __device__ __forceinline__ void adj_state(const AdjArgs<T>& A, const Column<T, D
             return;
         }
     }
-    const long long id = C.base + mm * C.stride;
+    const uint32_t off = C.cb + (uint32_t)mm * C.sb;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = A.u[f * A.fstride + id];
-    v = A.pk[id] * u[1 + DIR];
-    P = A.pk[A.fstride + id];
+    for (int f = 0; f < 5; ++f) u[f] = ld_off(C.u[f], off);
+    v = ld_off(C.pk[0], off) * u[1 + DIR];
+    P = ld_off(C.pk[1], off);
 }
 
 // weights at line position m: zero outside the grid unless periodic
@@ -137,9 +174,9 @@ __device__ __forceinline__ void adj_weight(const AdjArgs<T>& A, const Column<T, 
         mm = m % nd;
         if (mm < 0) mm += nd;
     }
-    const long long id = C.base + mm * C.stride;
+    const uint32_t off = C.cb + (uint32_t)mm * C.sb;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) w[f] = A.w[f * A.fstride + id];
+    for (int f = 0; f < 5; ++f) w[f] = ld_off(C.w[f], off);
 }
 
 }  // namespace
@@ -164,9 +201,13 @@ struct AdjGroup {
     static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? RH_ADJ_GROUP_F32_W5 : RH_ADJ_GROUP_OTHER;
 };
 
-template <class T, int ORDER, int DIR, int CLO, int CHI>
+template <class T, int ORDER, int DIR, int CLO, int CHI, bool HUB>
 __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R, NC = CHI - CLO;
+    // WENO5 gradient in the first differences (fewer instructions, more live
+    // values) except where the analytic-ghost branch leaves too few registers
+    // for it at three FP32 waves per SIMD
+    constexpr bool EFORM = !(sizeof(T) == 4 && HUB);
     const int nd = A.n[DIR];
     const bool periodic = A.bc == RH_BC_PERIODIC;
     int i_lo = k0 - R, i_hi = k1 + R - 2;
@@ -180,7 +221,10 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     const T eps = A.eps;
     const T half = (T)0.5;
 
-    // split fluxes of the group's components from a cell state
+    // doubled split fluxes F +- u of the group's components from a cell state:
+    // the reconstruction is homogeneous of degree one in (f, sqrt(eps)), so its
+    // gradient at (2 f, 4 eps) equals the gradient at (f, eps), bit for bit
+    // (all scalings are powers of two); the 1/2 of the split stays in finish
     auto group_flux = [&](const T u[5], T v, T P, T fp[NC], T fm[NC]) {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -189,8 +233,8 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
             if (c == 0) f = u[1 + DIR];
             else if (c == 4) f = u[4] * v;
             else f = u[c] * v + (c == 1 + DIR ? P : (T)0);
-            fp[q] = half * (f + u[c]);
-            fm[q] = half * (f - u[c]);
+            fp[q] = f + u[c];
+            fm[q] = f - u[c];
         }
     };
     // Owned position pos -> the cell whose adjoint it updates (outflow ghost
@@ -209,17 +253,17 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     int last_tgt = -1;
     T ubo[5], uf[5], pkf[5];
     auto fetch_cell = [&](int tgt) {
-        const long long id = C.base + (long long)tgt * C.stride;
+        const uint32_t off = C.cb + (uint32_t)tgt * C.sb;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) uf[f] = A.u[f * A.fstride + id];
+        for (int f = 0; f < 5; ++f) uf[f] = ld_off(C.u[f], off);
         if constexpr (CHI > 1) {
-            pkf[0] = A.pk[id];
+            pkf[0] = ld_off(C.pk[0], off);
 #pragma unroll
-            for (int q = 1; q < 5; ++q) pkf[q] = A.pk[(q + 1) * A.fstride + id];
+            for (int q = 1; q < 5; ++q) pkf[q] = ld_off(C.pk[q + 1], off);
         }
         if (tgt == last_tgt) return;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) ubo[f] = A.ub[f * A.fstride + id];
+        for (int f = 0; f < 5; ++f) ubo[f] = ld_off(C.ub[f], off);
     };
     // ub += scale * sum over the group of (d f+_c/du)^T a+_c + (d f-_c/du)^T a-_c
     auto finish = [&](int tgt, const T apj[NC], const T amj[NC]) {
@@ -248,11 +292,11 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
             for (int m = 0; m < 3; ++m) g[1 + m] += (sk + sp) * uf[1 + m];
             g[1 + DIR] += S * pkf[0];
         }
-        const long long id = C.base + (long long)tgt * C.stride;
+        const uint32_t off = C.cb + (uint32_t)tgt * C.sb;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             ubo[f] = ubo[f] + A.scale * g[f];
-            A.ub[f * A.fstride + id] = ubo[f];
+            st_off(C.ub[f], off, ubo[f]);
         }
         last_tgt = tgt;
     };
@@ -260,7 +304,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         T u[5], v, P, fp[NC], fm[NC];
-        adj_state<T, DIR>(A, C, i_lo - R + 1 + j, u, v, P);
+        adj_state<T, DIR, HUB>(A, C, i_lo - R + 1 + j, u, v, P);
         group_flux(u, v, P, fp, fm);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -283,7 +327,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
 #pragma unroll
         for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
     }
-    adj_state<T, DIR>(A, C, i_lo + R + 1, un, vn, Pn);
+    adj_state<T, DIR, HUB>(A, C, i_lo + R + 1, un, vn, Pn);
     for (int i = i_lo; i <= i_hi; ++i) {
         T wr[NC], unew[5];
 #pragma unroll
@@ -297,7 +341,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
 #pragma unroll
             for (int q = 0; q < NC; ++q) wn[q] = w5[CLO + q];
         }
-        adj_state<T, DIR>(A, C, i + R + 2, un, vn, Pn);
+        adj_state<T, DIR, HUB>(A, C, i + R + 2, un, vn, Pn);
         int tgt = 0;
         const bool own = target(i - R + 1, tgt);
         if (own) fetch_cell(tgt);
@@ -306,20 +350,27 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
             const T g = (wr[q] - wl[q]) * A.inv_h;
             wl[q] = wr[q];
             if constexpr (ORDER == 5) {
-                weno5_grad_acc<T>(wp[q][0], wp[q][1], wp[q][2], wp[q][3], wp[q][4], (T)4 * eps, g,
-                                  ap[q][0], ap[q][1], ap[q][2], ap[q][3], ap[q][4]);
-                weno5_grad_acc<T>(wm[q][5], wm[q][4], wm[q][3], wm[q][2], wm[q][1], (T)4 * eps, g,
-                                  am[q][5], am[q][4], am[q][3], am[q][2], am[q][1]);
+                if constexpr (EFORM) {
+                    weno5_grad_acc_e<T>(wp[q][0], wp[q][1], wp[q][2], wp[q][3], wp[q][4], (T)16 * eps, g,
+                                        ap[q][0], ap[q][1], ap[q][2], ap[q][3], ap[q][4]);
+                    weno5_grad_acc_e<T>(wm[q][5], wm[q][4], wm[q][3], wm[q][2], wm[q][1], (T)16 * eps, g,
+                                        am[q][5], am[q][4], am[q][3], am[q][2], am[q][1]);
+                } else {
+                    weno5_grad_acc<T>(wp[q][0], wp[q][1], wp[q][2], wp[q][3], wp[q][4], (T)16 * eps, g,
+                                      ap[q][0], ap[q][1], ap[q][2], ap[q][3], ap[q][4]);
+                    weno5_grad_acc<T>(wm[q][5], wm[q][4], wm[q][3], wm[q][2], wm[q][1], (T)16 * eps, g,
+                                      am[q][5], am[q][4], am[q][3], am[q][2], am[q][1]);
+                }
             } else {
                 T sv[7], o[7];
 #pragma unroll
                 for (int j = 0; j < 7; ++j) { sv[j] = wp[q][j]; o[j] = (T)0; }
-                weno7_grad_acc<T>(sv, eps, g, o);
+                weno7_grad_acc<T>(sv, (T)4 * eps, g, o);
 #pragma unroll
                 for (int j = 0; j < 7; ++j) ap[q][j] += o[j];
 #pragma unroll
                 for (int j = 0; j < 7; ++j) { sv[j] = wm[q][7 - j]; o[j] = (T)0; }
-                weno7_grad_acc<T>(sv, eps, g, o);
+                weno7_grad_acc<T>(sv, (T)4 * eps, g, o);
 #pragma unroll
                 for (int j = 0; j < 7; ++j) am[q][7 - j] += o[j];
             }
@@ -368,13 +419,13 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     }
 }
 
-template <class T, int ORDER, int DIR, int CLO>
+template <class T, int ORDER, int DIR, int CLO, bool HUB>
 __device__ __forceinline__ void adj_passes(const AdjArgs<T>& A, const Column<T, DIR>& C, int k0, int k1) {
     if constexpr (CLO < 5) {
         constexpr int GS = AdjGroup<T, ORDER>::value;
         constexpr int CHI = CLO + GS < 5 ? CLO + GS : 5;
-        adj_pass<T, ORDER, DIR, CLO, CHI>(A, C, k0, k1);
-        adj_passes<T, ORDER, DIR, CHI>(A, C, k0, k1);
+        adj_pass<T, ORDER, DIR, CLO, CHI, HUB>(A, C, k0, k1);
+        adj_passes<T, ORDER, DIR, CHI, HUB>(A, C, k0, k1);
     }
 }
 
@@ -385,13 +436,13 @@ struct AdjMinBlocks {
     static constexpr int value = sizeof(T) == 4 ? 3 : 1;
 };
 
-template <class T, int ORDER, int DIR>
+template <class T, int ORDER, int DIR, bool HUB>
 __global__ void __launch_bounds__(256, (AdjMinBlocks<T>::value)) adj_roll(AdjArgs<T> A) {
     Column<T, DIR> C;
     if (!column_of<T, DIR>(A, blockIdx.x * 256u + threadIdx.x, C)) return;
     const int k0 = blockIdx.y * A.seg;
     const int k1 = min(k0 + A.seg, A.n[DIR]);
-    adj_passes<T, ORDER, DIR, 0>(A, C, k0, k1);
+    adj_passes<T, ORDER, DIR, 0, HUB>(A, C, k0, k1);
 }
 
 template <class T>
@@ -489,8 +540,8 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
             f[4] = u[4] * v;
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
-                fp[c] = half * (f[c] + u[c]);
-                fm[c] = half * (f[c] - u[c]);
+                fp[c] = f[c] + u[c];   // doubled split fluxes (eps scaled by 4 below)
+                fm[c] = f[c] - u[c];
             }
         }
 #pragma unroll
@@ -531,9 +582,9 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
                 const T g = (sw[c][fy][fl + 1] - sw[c][fy][fl]) * A.inv_h;
                 if constexpr (ORDER == 5) {
                     weno5_grad_acc_e<T>(sfp[c][fy][fl], sfp[c][fy][fl + 1], sfp[c][fy][fl + 2], sfp[c][fy][fl + 3],
-                                      sfp[c][fy][fl + 4], (T)4 * A.eps, g, op[0], op[1], op[2], op[3], op[4]);
+                                      sfp[c][fy][fl + 4], (T)16 * A.eps, g, op[0], op[1], op[2], op[3], op[4]);
                     weno5_grad_acc_e<T>(sfm[c][fy][fl + 5], sfm[c][fy][fl + 4], sfm[c][fy][fl + 3],
-                                      sfm[c][fy][fl + 2], sfm[c][fy][fl + 1], (T)4 * A.eps, g, om[4], om[3],
+                                      sfm[c][fy][fl + 2], sfm[c][fy][fl + 1], (T)16 * A.eps, g, om[4], om[3],
                                       om[2], om[1], om[0]);
                 } else {
                     T sv[7], o[7];
@@ -542,7 +593,7 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
                         sv[j] = sfp[c][fy][fl + j];
                         o[j] = (T)0;
                     }
-                    weno7_grad_acc<T>(sv, A.eps, g, o);
+                    weno7_grad_acc<T>(sv, (T)4 * A.eps, g, o);
 #pragma unroll
                     for (int j = 0; j < 7; ++j) op[j] = o[j];
 #pragma unroll
@@ -550,7 +601,7 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
                         sv[j] = sfm[c][fy][fl + 7 - j];
                         o[j] = (T)0;
                     }
-                    weno7_grad_acc<T>(sv, A.eps, g, o);
+                    weno7_grad_acc<T>(sv, (T)4 * A.eps, g, o);
 #pragma unroll
                     for (int j = 0; j < 7; ++j) om[6 - j] = o[j];
                 }
@@ -691,12 +742,14 @@ hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s)
     const unsigned gy = (nd + a.seg - 1) / a.seg;
     const dim3 grid(gx, gy), block(256);
     if ((dir != 1 && dir != 2) || !a.pk) return hipErrorInvalidValue;
+    const bool hub = a.bc == RH_BC_HUBBLE;
+    auto go = [&](auto kernel) { kernel<<<grid, block, 0, s>>>(a); };
     if (order == 5) {
-        if (dir == 1) adj_roll<T, 5, 1><<<grid, block, 0, s>>>(a);
-        else adj_roll<T, 5, 2><<<grid, block, 0, s>>>(a);
+        if (dir == 1) hub ? go(adj_roll<T, 5, 1, true>) : go(adj_roll<T, 5, 1, false>);
+        else hub ? go(adj_roll<T, 5, 2, true>) : go(adj_roll<T, 5, 2, false>);
     } else {
-        if (dir == 1) adj_roll<T, 7, 1><<<grid, block, 0, s>>>(a);
-        else adj_roll<T, 7, 2><<<grid, block, 0, s>>>(a);
+        if (dir == 1) hub ? go(adj_roll<T, 7, 1, true>) : go(adj_roll<T, 7, 1, false>);
+        else hub ? go(adj_roll<T, 7, 2, true>) : go(adj_roll<T, 7, 2, false>);
     }
     return hipGetLastError();
 }

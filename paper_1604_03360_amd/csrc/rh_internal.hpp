@@ -120,4 +120,16 @@ int choose_tile_x(int nx, int ghosts);
 // rolling segment length along y or z
 int choose_segment(int n, int ncols);
 
+// Load / store through a uniform base pointer and a 32-bit byte offset (the
+// plan limits one field to < 4 GiB), so that address arithmetic stays 32-bit
+// per lane and the base lives in scalar registers.
+template <class T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
+    return *(const T*)((const char*)base + off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
+    *(T*)((char*)base + off) = v;
+}
+
 }  // namespace rh

@@ -192,17 +192,6 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
 // ---------------------------------------------------------------------------
 // y / z sweeps: per-lane rolling register window
 // ---------------------------------------------------------------------------
-// Load through a uniform base pointer and a 32-bit byte offset (the plan limits
-// one field to < 4 GiB), so that address arithmetic stays 32-bit per lane.
-template <class T>
-__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
-    return *(const T*)((const char*)base + off);
-}
-template <class T>
-__device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
-    *(T*)((char*)base + off) = v;
-}
-
 // bx: 256-lane chunk of the (x, w) plane; by: segment along the sweep axis
 template <class T, int ORDER, int DIR>
 __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned bx, int by) {
