@@ -54,20 +54,31 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, precision):
-    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources (else None)."""
+def load_profile(precision):
+    """Per-kernel counters of the committed rocprofv3 PMC summary (HBM bytes and
+    VALU wave instructions per launch), if it was taken on the current kernel
+    sources (else {})."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic_blob256.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         rec = json.load(open(path))
     except ValueError:
-        return None
+        return {}
     if rec.get("source_hash") != source_hash():
-        return None
-    ent = rec.get("kernels", {}).get(precision, {}).get(kernel)
+        return {}
+    return rec.get("kernels", {}).get(precision, {})
+
+
+def load_traffic(kernel, precision):
+    """HBM traffic per launch of one sweep class from the PMC summary, or None."""
+    ent = load_profile(precision).get(kernel)
     return None if ent is None else ent.get("bytes_per_launch")
+
+
+# one VALU wave instruction per CU per cycle is the unpacked issue rate
+# (4 SIMDs, a wave64 instruction every 4 cycles each): 256 CUs x 2.4 GHz
+VALU_WAVE_ISSUE_PER_S = 256 * 2.4e9
 
 
 def run_gpu(spec, precision, steps, warmup):
@@ -254,11 +265,32 @@ def roofline(run, precision, order, ncell):
         hbm["counted_bytes_per_launch"] = traffic
         hbm["counted_GBps"] = round(traffic / avg_s / 1e9, 1)
         hbm["counted_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    # whole step: algorithmic bytes (read the stage input in all three stages and
+    # u^n in stages 2 and 3, write each stage's output: 40 values per cell-update)
+    # and, from the PMC summary, the counted bytes of all nine sweeps
+    step_s = run["ms_per_step"] * 1e-3
+    alg_step = 40.0 * elem * ncell
+    hbm["step_alg"] = {"bytes": alg_step, "GBps": round(alg_step / step_s / 1e9, 1),
+                       "frac": round(alg_step / step_s / 1e9 / HBM_PEAK_GBS, 4)}
+    prof = load_profile(precision)
+    if all(k in prof and "bytes_per_launch" in prof[k] for k in ("sweep_x", "sweep_y", "sweep_z")):
+        counted = 3.0 * sum(prof[k]["bytes_per_launch"] for k in ("sweep_x", "sweep_y", "sweep_z"))
+        hbm["step_counted"] = {"bytes": counted, "GBps": round(counted / step_s / 1e9, 1),
+                               "frac": round(counted / step_s / 1e9 / HBM_PEAK_GBS, 4)}
+    valu = None
+    if dom in prof and "SQ_INSTS_VALU" in prof[dom]:
+        wi = prof[dom]["SQ_INSTS_VALU"]
+        rate = wi / avg_s / VALU_WAVE_ISSUE_PER_S
+        valu = {"kernel": dom, "wave_instr_per_launch": wi, "instr_per_cell": round(wi * 64 / ncell, 1),
+                "wave_instr_per_cu_cycle": round(rate, 4),
+                "frac_of_unpacked_issue": round(rate, 4),
+                # the FP32 peak counts packed dual FP32; FP64 issues at the unpacked rate
+                "frac_of_peak": round(rate / 2.0, 4) if precision == "fp32" else round(rate, 4)}
     return dom, {
         "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4), "traffic": traffic,
         "kernel": dom, "avg_launch_ms": round(ms / launches, 4),
-        "flops_per_cell": sweep_flops_per_cell(order),
+        "flops_per_cell": sweep_flops_per_cell(order), "valu": valu,
     }, hbm
 
 
