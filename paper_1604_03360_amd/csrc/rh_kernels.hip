@@ -225,12 +225,27 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
         }
     };
 
+    // The stage combine of cell k needs the stage input u(k), loaded R + 1 steps
+    // earlier as the window's newest cell; by then a strided sweep has streamed
+    // several MB through L2 and a second load would go to memory again.  Each
+    // lane therefore keeps u of its last R + 1 cells in a private LDS ring
+    // (slot = cell mod D, lanes in consecutive words; no barrier, a lane reads
+    // only what it wrote).
+    constexpr int D = R + 1 <= 4 ? 4 : 8;
+    __shared__ T uring[D][5][256];
+    const bool combine = A.stage != STAGE_WRITE_L;
+    auto ring_put = [&](int m, const T uu[5]) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) uring[m & (D - 1)][f][threadIdx.x] = uu[f];
+    };
+
     // window of interface k-1/2: cells k-R .. k+R-1
     T wp[5][W], wm[5][W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         T u[5], fp[5], fm[5];
         fetch(k0 - R + j, u);
+        if (j >= R && combine) ring_put(k0 - R + j, u);
         split_flux<T, DIR>(u, fp, fm, clamped);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -252,6 +267,7 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
 #pragma unroll
         for (int f = 0; f < 5; ++f) u[f] = nxt[f];
         fetch(k + 1 + R, nxt);   // next iteration's new cell, in flight during this one
+        if (combine) ring_put(k + R, u);
         // epilogue operands of cell k: FP32 issues them before the arithmetic;
         // FP64 loads them after it to keep the register window within 256 VGPRs
         const uint32_t off = cb + (uint32_t)k * sb;
@@ -260,7 +276,7 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 lo[c] = A.first ? (T)0 : ld_off(A.lacc + c * F, off);
-                us[c] = A.stage != STAGE_WRITE_L ? ld_off(A.us + c * F, off) : (T)0;
+                us[c] = combine ? uring[k & (D - 1)][c][threadIdx.x] : (T)0;
                 u0[c] = A.stage >= STAGE_2 ? ld_off(A.u0 + c * F, off) : (T)0;
             }
         };
