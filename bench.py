@@ -54,10 +54,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def load_profile(precision):
+def load_profile(precision, order=5):
     """Per-kernel counters of the committed rocprofv3 PMC summary (HBM bytes and
     VALU wave instructions per launch), if it was taken on the current kernel
-    sources (else {})."""
+    sources and the same scheme (else {})."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic_blob256.json")
     if not os.path.exists(path):
         return {}
@@ -65,14 +65,14 @@ def load_profile(precision):
         rec = json.load(open(path))
     except ValueError:
         return {}
-    if rec.get("source_hash") != source_hash():
+    if rec.get("source_hash") != source_hash() or rec.get("order", 5) != order:
         return {}
     return rec.get("kernels", {}).get(precision, {})
 
 
-def load_traffic(kernel, precision):
+def load_traffic(kernel, precision, order=5):
     """HBM traffic per launch of one sweep class from the PMC summary, or None."""
-    ent = load_profile(precision).get(kernel)
+    ent = load_profile(precision, order).get(kernel)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -253,7 +253,7 @@ def roofline(run, precision, order, ncell):
     achieved = flops / avg_s / 1e12
     peak = ALU_PEAK_TFLOPS[precision]
     alg_bytes = SWEEP_VALUES[dom] * elem * ncell
-    traffic = load_traffic(dom, precision)
+    traffic = load_traffic(dom, precision, order)
     hbm = {
         "kernel": dom, "design_bytes_per_launch": alg_bytes,
         "achieved_GBps": round(alg_bytes / avg_s / 1e9, 1), "peak_GBps": HBM_PEAK_GBS,
@@ -272,7 +272,7 @@ def roofline(run, precision, order, ncell):
     alg_step = 40.0 * elem * ncell
     hbm["step_alg"] = {"bytes": alg_step, "GBps": round(alg_step / step_s / 1e9, 1),
                        "frac": round(alg_step / step_s / 1e9 / HBM_PEAK_GBS, 4)}
-    prof = load_profile(precision)
+    prof = load_profile(precision, order)
     if all(k in prof and "bytes_per_launch" in prof[k] for k in ("sweep_x", "sweep_y", "sweep_z")):
         counted = 3.0 * sum(prof[k]["bytes_per_launch"] for k in ("sweep_x", "sweep_y", "sweep_z"))
         hbm["step_counted"] = {"bytes": counted, "GBps": round(counted / step_s / 1e9, 1),
@@ -337,6 +337,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-weno7", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (reference "
                          "for scaling hardware byte counters)")
@@ -369,6 +370,18 @@ def main():
         r64 = run_gpu(spec, "fp64", args.steps, args.warmup)
         print("bench: fp64 %.4g cell-updates/s (%.3f ms/step)" % (r64["value"], r64["ms_per_step"]),
               file=sys.stderr, flush=True)
+    w7 = None
+    if args.scheme == 5 and not args.no_weno7:
+        # the same blob with WENO7, FP32 and FP64 (steps replayed from the graph)
+        spec7 = inputs.blob(n=args.n, order=7)
+        w7 = {}
+        for prec in ("fp32", "fp64"):
+            r = run_gpu(spec7, prec, min(args.steps, 10), min(args.warmup, 2))
+            w7[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                        "kernels_ms_per_step": {k: v[0] / min(args.steps, 10) for k, v in r["kernels"].items()}}
+        w7["fp32_over_fp64"] = w7["fp32"]["value"] / w7["fp64"]["value"]
+        print("bench: WENO7 fp32 %.4g, fp64 %.4g cell-updates/s" % (w7["fp32"]["value"], w7["fp64"]["value"]),
+              file=sys.stderr, flush=True)
     adj = None
     if not args.no_adjoint:
         adj = run_adjoint(spec, "fp32", 3)
@@ -400,6 +413,8 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in r32["kernels"].items()},
         "counters": r32["counters"],
     }
+    if w7 is not None:
+        out["weno7"] = w7
     if adj is not None:
         out["adjoint"] = dict(adj, workload="same grid, FP32: adjoint of one SSP-RK3 step with its "
                                            "stage states resident / one forward step; with the stage "
