@@ -55,6 +55,23 @@ __device__ __forceinline__ double fast_rcp(double x) {
     return fma(r, e, r);
 }
 
+// Square root of a positive normal double (no rescaling of tiny or huge
+// arguments, no special cases): the hardware reciprocal square root y refined
+// by one coupled Goldschmidt step on (g, h) ~ (sqrt(x), 1/(2 sqrt(x))) and two
+// Newton corrections g <- g + (x - g^2) h.  Used for 4E^2 - 3M^2 >= E^2 with E
+// above the floor, which is always in the normal range.
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 // Closed-form primitive recovery for p = e/3 (FP64):
 //   M^2 = |M|^2, D = sqrt(4E^2 - 3M^2), v = 3M/(2E + D), p = (E^2 - M^2)/(E + D).
 // Only the velocity along the sweep axis and p are needed for the flux.  Both
@@ -77,7 +94,7 @@ __device__ __forceinline__ void recover_vp(double E, double Mx, double My, doubl
         M2 = cap;
         ++clamped;
     }
-    const double D = sqrt(4.0 * E2 - 3.0 * M2);
+    const double D = sqrt_pos(4.0 * E2 - 3.0 * M2);
     const double a = 2.0 * E + D;
     const double b = E + D;
     const double r = fast_rcp(a * b);
