@@ -322,7 +322,22 @@ def cpu_baseline(spec, nsteps):
         oracle.set_threads(cores)
     out["single_thread"] = {"value": 96 ** 3 / el1, "unit": "cell-updates/s", "cores": 1,
                             "sample": "1 SSP-RK3 step of the blob at 96^3 (dx 0.1), FP64, %.1f s" % el1}
+    # the whole 200-step blob run at these rates, and the host it was measured on
+    out["full_run_200_steps_s"] = {"all_cores": 200 * ncell / out["value"],
+                                   "one_thread": 200 * ncell / out["single_thread"]["value"]}
+    out["host"] = {"nproc": os.cpu_count(), "cpu_model": cpu_model()}
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
