@@ -358,7 +358,7 @@ def main():
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the path has no multi-GPU mode); "
+        print("bench.py: this benchmark measures one GPU only (the path has no multi-GPU mode); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

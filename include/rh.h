@@ -39,7 +39,7 @@ typedef int rh_status;
 #define RH_E_NOMEM   -2  /* a library-owned device allocation failed */
 #define RH_E_HIP     -3  /* a HIP runtime call or kernel launch failed (message has details) */
 #define RH_E_STATE   -4  /* call out of order, e.g. stepping a plan with no bound buffers */
-#define RH_E_NOTSUP  -5  /* valid request that this build does not support */
+#define RH_E_NOTSUP  -5  /* valid request that this library does not support */
 #define RH_E_PHYS    -6  /* strict mode: a primitive-recovery floor acted or a value is not finite */
 
 /* Arithmetic of a plan.  RH_PREC_FP64: storage, stencil and Runge-Kutta in FP64.
