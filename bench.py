@@ -55,10 +55,11 @@ def source_hash():
 
 
 def load_profile(precision, order=5):
-    """Per-kernel counters of the committed rocprofv3 PMC summary (HBM bytes and
-    VALU wave instructions per launch), if it was taken on the current kernel
-    sources and the same scheme (else {})."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_blob256.json")
+    """Per-kernel counters of the committed rocprofv3 PMC summary of the scheme
+    (HBM bytes and VALU wave instructions per launch), if it was taken on the
+    current kernel sources (else {})."""
+    name = "pmc_traffic_blob256.json" if order == 5 else "pmc_traffic_blob256_weno7.json"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return {}
     try:
@@ -392,7 +393,8 @@ def main():
         w7 = {}
         for prec in ("fp32", "fp64"):
             r = run_gpu(spec7, prec, min(args.steps, 10), min(args.warmup, 2))
-            w7[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+            _, roof7, hbm7 = roofline(r, prec, 7, ncell)
+            w7[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "roofline": roof7, "hbm": hbm7,
                         "kernels_ms_per_step": {k: v[0] / min(args.steps, 10) for k, v in r["kernels"].items()}}
         w7["fp32_over_fp64"] = w7["fp32"]["value"] / w7["fp64"]["value"]
         print("bench: WENO7 fp32 %.4g, fp64 %.4g cell-updates/s" % (w7["fp32"]["value"], w7["fp64"]["value"]),
