@@ -386,35 +386,55 @@ def main():
         r64 = run_gpu(spec, "fp64", args.steps, args.warmup)
         print("bench: fp64 %.4g cell-updates/s (%.3f ms/step)" % (r64["value"], r64["ms_per_step"]),
               file=sys.stderr, flush=True)
-    w7 = None
-    if args.scheme == 5 and not args.no_weno7:
+    def side_leg(name, fn):
+        # the side legs add context to the headline figure; a failure in one of
+        # them (an error status from the library, say) is reported in its block
+        # instead of losing the whole line
+        try:
+            return fn()
+        except Exception as e:  # noqa: BLE001
+            import traceback
+            traceback.print_exc()
+            print("bench: %s leg failed: %s" % (name, e), file=sys.stderr, flush=True)
+            return {"error": "%s: %s" % (type(e).__name__, e)}
+
+    def weno7_leg():
         # the same blob with WENO7, FP32 and FP64 (steps replayed from the graph)
         spec7 = inputs.blob(n=args.n, order=7)
-        w7 = {}
+        w = {}
         for prec in ("fp32", "fp64"):
             r = run_gpu(spec7, prec, min(args.steps, 10), min(args.warmup, 2))
             _, roof7, hbm7 = roofline(r, prec, 7, ncell)
-            w7[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "roofline": roof7, "hbm": hbm7,
-                        "kernels_ms_per_step": {k: v[0] / min(args.steps, 10) for k, v in r["kernels"].items()}}
-        w7["fp32_over_fp64"] = w7["fp32"]["value"] / w7["fp64"]["value"]
-        print("bench: WENO7 fp32 %.4g, fp64 %.4g cell-updates/s" % (w7["fp32"]["value"], w7["fp64"]["value"]),
+            w[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "roofline": roof7, "hbm": hbm7,
+                       "kernels_ms_per_step": {k: v[0] / min(args.steps, 10) for k, v in r["kernels"].items()}}
+        w["fp32_over_fp64"] = w["fp32"]["value"] / w["fp64"]["value"]
+        print("bench: WENO7 fp32 %.4g, fp64 %.4g cell-updates/s" % (w["fp32"]["value"], w["fp64"]["value"]),
               file=sys.stderr, flush=True)
-    adj = None
-    if not args.no_adjoint:
-        adj = run_adjoint(spec, "fp32", 3)
+        return w
+
+    def adjoint_leg():
+        a = run_adjoint(spec, "fp32", 3)
         print("bench: adjoint step %.3f ms (%.3f ms with recomputation) vs forward step %.3f ms "
-              "(ratio %.2f, %.2f)" % (adj["step_vjp_ms"], adj["step_vjp_recompute_ms"], adj["step_ms"],
-                                      adj["ratio"], adj["ratio_with_recompute"]), file=sys.stderr, flush=True)
-    diff = None
-    if not args.no_adjoint:
-        diff = run_diff()
+              "(ratio %.2f, %.2f)" % (a["step_vjp_ms"], a["step_vjp_recompute_ms"], a["step_ms"],
+                                      a["ratio"], a["ratio_with_recompute"]), file=sys.stderr, flush=True)
+        return a
+
+    def diff_leg():
+        d = run_diff()
         print("bench: 96^3 differentiable run: forward %.3f s, backward %.3f s; adjoint step ratio %.2f"
-              % (diff["forward_s"], diff["backward_s"], diff["adjoint_step_ratio"]), file=sys.stderr, flush=True)
-    bat = None
-    if not args.no_batch:
-        bat = run_batch(min(args.steps, 10), 2)
-        print("bench: batch %.4g cell-updates/s (%.3f ms/step)" % (bat["value"], bat["ms_per_step"]),
+              % (d["forward_s"], d["backward_s"], d["adjoint_step_ratio"]), file=sys.stderr, flush=True)
+        return d
+
+    def batch_leg():
+        b = run_batch(min(args.steps, 10), 2)
+        print("bench: batch %.4g cell-updates/s (%.3f ms/step)" % (b["value"], b["ms_per_step"]),
               file=sys.stderr, flush=True)
+        return b
+
+    w7 = side_leg("WENO7", weno7_leg) if args.scheme == 5 and not args.no_weno7 else None
+    adj = side_leg("adjoint", adjoint_leg) if not args.no_adjoint else None
+    diff = side_leg("differentiable run", diff_leg) if not args.no_adjoint else None
+    bat = side_leg("batch", batch_leg) if not args.no_batch else None
     dom, roof, hbm = roofline(r32, "fp32", args.scheme, ncell)
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "cell-updates/s", "n_gpus": 1,
@@ -447,7 +467,7 @@ def main():
                        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in r64["kernels"].items()}}
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+        out["cpu_baseline"] = side_leg("CPU baseline", lambda: cpu_baseline(spec, args.cpu_steps))
     print(json.dumps(out), flush=True)
 
 
