@@ -219,24 +219,29 @@ __device__ __forceinline__ T weno7(T s0, T s1, T s2, T s3, T s4, T s5, T s6, T e
     g1 *= g1;
     g2 *= g2;
     g3 *= g3;
-    T w0, w1, w2, w3;
     if constexpr (sizeof(T) == 8) {
         // FP64: one reciprocal via products of the other three squared terms
         const T g01 = g0 * g1, g23 = g2 * g3;
-        w0 = (T)(1.0 / 35.0) * (g1 * g23);
-        w1 = (T)(12.0 / 35.0) * (g0 * g23);
-        w2 = (T)(18.0 / 35.0) * (g01 * g3);
-        w3 = (T)(4.0 / 35.0) * (g01 * g2);
+        const T w0 = (T)(1.0 / 35.0) * (g1 * g23);
+        const T w1 = (T)(12.0 / 35.0) * (g0 * g23);
+        const T w2 = (T)(18.0 / 35.0) * (g01 * g3);
+        const T w3 = (T)(4.0 / 35.0) * (g01 * g2);
+        const T num = (w0 * dq0 + w1 * dq1) + (w2 * dq2 + w3 * dq3);
+        const T den = (w0 + w1) + (w2 + w3);
+        return s3 + num * fast_rcp(den);
     } else {
-        // FP32: products of three squared terms can overflow; use reciprocals
-        w0 = (T)(1.0 / 35.0) * fast_rcp(g0);
-        w1 = (T)(12.0 / 35.0) * fast_rcp(g1);
-        w2 = (T)(18.0 / 35.0) * fast_rcp(g2);
-        w3 = (T)(4.0 / 35.0) * fast_rcp(g3);
+        // FP32: products of three squared terms can overflow, so one reciprocal
+        // per weight; the linear weights 35 d = (1, 12, 18, 4) are folded into
+        // the candidates (12 dq1 = 4 D3 - D2 + 3 D4, 18 dq2 = 3/2 (D3 - D5) + 9 D4,
+        // 4 dq3 = 3 D4 - 4/3 D5 + 1/3 D6) and the weight sum, the 1/35 cancels
+        const T r0 = fast_rcp(g0), r1 = fast_rcp(g1), r2 = fast_rcp(g2), r3 = fast_rcp(g3);
+        const T q1 = ((T)4 * D3 - D2) + (T)3 * D4;
+        const T q2 = (T)1.5 * (D3 - D5) + (T)9 * D4;
+        const T q3 = ((T)3 * D4 - (T)(4.0 / 3.0) * D5) + (T)(1.0 / 3.0) * D6;
+        const T num = (r0 * dq0 + r1 * q1) + (r2 * q2 + r3 * q3);
+        const T den = (r0 + (T)12 * r1) + ((T)18 * r2 + (T)4 * r3);
+        return s3 + num * fast_rcp(den);
     }
-    const T num = (w0 * dq0 + w1 * dq1) + (w2 * dq2 + w3 * dq3);
-    const T den = (w0 + w1) + (w2 + w3);
-    return s3 + num * fast_rcp(den);
 }
 
 }  // namespace rh
