@@ -42,8 +42,11 @@ def sweep_flops_per_cell(order):
 
 # HBM values per cell that each sweep class must move in this split-sweep design:
 # x sweep reads u (5) and writes L (5); y sweep reads u, L and writes L (15);
-# z sweep reads u, L, u^n and writes the new state (20; 15 in stage 1).
-SWEEP_VALUES = {"sweep_x": 10.0, "sweep_y": 15.0, "sweep_z": (15.0 + 20.0 + 20.0) / 3.0}
+# z sweep reads u, L, u^n and writes the new state (20; 15 in stage 1); the
+# fused x-y sweep reads u and writes L (10).
+SWEEP_VALUES = {"sweep_x": 10.0, "sweep_y": 15.0, "sweep_z": (15.0 + 20.0 + 20.0) / 3.0, "sweep_xy": 10.0}
+# directional sweeps per launch of each class (the fused class does two)
+SWEEP_AXES = {"sweep_x": 1, "sweep_y": 1, "sweep_z": 1, "sweep_xy": 2}
 
 
 def source_hash():
@@ -246,11 +249,12 @@ def run_batch(steps, warmup):
 
 def roofline(run, precision, order, ncell):
     elem = 4 if precision == "fp32" else 8
-    kern = {k: v for k, v in run["kernels"].items() if k.startswith("sweep")}
+    kern = {k: v for k, v in run["kernels"].items() if k.startswith("sweep") and v[1] > 0}
     dom = max(kern, key=lambda k: kern[k][0])
     ms, launches = kern[dom]
     avg_s = ms / launches * 1e-3
-    flops = sweep_flops_per_cell(order) * ncell
+    flops_cell = SWEEP_AXES[dom] * sweep_flops_per_cell(order)
+    flops = flops_cell * ncell
     achieved = flops / avg_s / 1e12
     peak = ALU_PEAK_TFLOPS[precision]
     alg_bytes = SWEEP_VALUES[dom] * elem * ncell
@@ -268,14 +272,15 @@ def roofline(run, precision, order, ncell):
         hbm["counted_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
     # whole step: algorithmic bytes (read the stage input in all three stages and
     # u^n in stages 2 and 3, write each stage's output: 40 values per cell-update)
-    # and, from the PMC summary, the counted bytes of all nine sweeps
+    # and, from the PMC summary, the counted bytes of all sweep launches
     step_s = run["ms_per_step"] * 1e-3
     alg_step = 40.0 * elem * ncell
     hbm["step_alg"] = {"bytes": alg_step, "GBps": round(alg_step / step_s / 1e9, 1),
                        "frac": round(alg_step / step_s / 1e9 / HBM_PEAK_GBS, 4)}
     prof = load_profile(precision, order)
-    if all(k in prof and "bytes_per_launch" in prof[k] for k in ("sweep_x", "sweep_y", "sweep_z")):
-        counted = 3.0 * sum(prof[k]["bytes_per_launch"] for k in ("sweep_x", "sweep_y", "sweep_z"))
+    if all(k in prof and "bytes_per_launch" in prof[k] for k in kern):
+        # every sweep class of the step, three launches each (one per stage)
+        counted = 3.0 * sum(prof[k]["bytes_per_launch"] for k in kern)
         hbm["step_counted"] = {"bytes": counted, "GBps": round(counted / step_s / 1e9, 1),
                                "frac": round(counted / step_s / 1e9 / HBM_PEAK_GBS, 4)}
     valu = None
@@ -291,7 +296,7 @@ def roofline(run, precision, order, ncell):
         "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4), "traffic": traffic,
         "kernel": dom, "avg_launch_ms": round(ms / launches, 4),
-        "flops_per_cell": sweep_flops_per_cell(order), "valu": valu,
+        "flops_per_cell": flops_cell, "valu": valu,
     }, hbm
 
 

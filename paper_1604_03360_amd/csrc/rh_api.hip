@@ -143,7 +143,22 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
         return timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_combine<T>(a, p->stream); },
                             "combine launch");
     }
-    for (int i = 0; i < na; ++i) {
+    int i0 = 0;
+    if (na >= 2 && active[0] == 0 && active[1] == 1 && rh::sweep_xy_applies(p->d.scheme, n, p->d.bc[0])) {
+        // x and y in one launch
+        rh::SweepArgs<T> b = a;
+        b.first = 1;
+        b.stage = na == 2 ? stage : rh::STAGE_WRITE_L;
+        b.bc = p->d.bc[1];
+        b.inv_h = (T)(1.0 / h[1]);
+        const T inv_hx = (T)(1.0 / h[0]);
+        rh_status st = timed_launch(p, RH_KERNEL_SWEEP_XY,
+                                    [&] { return rh::launch_sweep_xy<T>(p->d.scheme, b, inv_hx, p->stream); },
+                                    "sweep launch");
+        if (st != RH_OK) return st;
+        i0 = 2;
+    }
+    for (int i = i0; i < na; ++i) {
         const int d = active[i];
         rh::SweepArgs<T> b = a;
         b.first = i == 0;

@@ -102,6 +102,39 @@ __device__ __forceinline__ void recover_vp(double E, double Mx, double My, doubl
     p = (E2 - M2) * a * r;
 }
 
+// The same recovery for two sweep axes at once: kap and the (capped) momenta
+// such that v_d = kap * Ms_d for every axis d, with the arithmetic of
+// recover_vp (so v_d is bitwise the value recover_vp<d> returns).
+__device__ __forceinline__ void recover_kp(double E, double Mx, double My, double Mz, double& kap,
+                                           double& Mxs, double& Mys, double& p, unsigned& clamped) {
+    if (E < kEFloor) {
+        kap = 0.0;
+        Mxs = 0.0;
+        Mys = 0.0;
+        p = (E > 0.0 ? E : 0.0) / 3.0;
+        ++clamped;
+        return;
+    }
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    const double E2 = E * E;
+    const double cap = (1.0 - kVDelta) * E * E;
+    Mxs = Mx;
+    Mys = My;
+    if (M2 > cap) {
+        const double sc = sqrt(cap / M2);
+        Mxs *= sc;
+        Mys *= sc;
+        M2 = cap;
+        ++clamped;
+    }
+    const double D = sqrt_pos(4.0 * E2 - 3.0 * M2);
+    const double a = 2.0 * E + D;
+    const double b = E + D;
+    const double r = fast_rcp(a * b);
+    kap = 3.0 * b * r;
+    p = (E2 - M2) * a * r;
+}
+
 // Split fluxes f+- = (F_d(u) +- u) / 2 of one cell along axis DIR, given the
 // velocity along DIR and the pressure, returned doubled (F_d +- u).
 //

@@ -120,6 +120,14 @@ int choose_tile_x(int nx, int ghosts);
 // rolling segment length along y or z
 int choose_segment(int n, int ncols);
 
+// Fused x and y sweeps (one launch doing both axes, bitwise the result of the
+// x sweep followed by the y sweep): applies to WENO5 grids with a periodic x
+// axis of 64, 128, 192 or 256 cells and more than one cell along y.
+bool sweep_xy_applies(int order, const int n[3], int bc_x);
+// a: the y sweep's arguments (first = 1; bc, inv_h of y); inv_hx = 1 / dx.
+template <class T>
+hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s);
+
 // Load / store through a uniform base pointer and a 32-bit byte offset (the
 // plan limits one field to < 4 GiB), so that address arithmetic stays 32-bit
 // per lane and the base lives in scalar registers.

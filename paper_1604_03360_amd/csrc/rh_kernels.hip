@@ -616,6 +616,158 @@ static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fused x and y sweeps (periodic x, nx a multiple of 64 up to 256, WENO5)
+// ---------------------------------------------------------------------------
+// A block holds whole x rows (lane = x) of one z plane and rolls along a y
+// segment like sweep_roll_body.  Each row that enters the y window is
+// recovered once (FP64) for both axes; when the row is owned its x split fluxes
+// go to LDS (with periodic halo copies), every lane reconstructs its right x
+// face, the face fluxes are exchanged through LDS and the row's x part of L is
+// kept in an LDS ring until the y face of that row is done R steps later.  L is
+// the x part plus the y part, summed in that order as in the split sweeps, so
+// the result is bitwise that of sweep_x followed by sweep_roll<1>.
+template <class T, int ORDER>
+__global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_xy(SweepArgs<T> A, T inv_hx) {
+    constexpr int R = (ORDER + 1) / 2, W = 2 * R;
+    constexpr int D = R + 1 <= 4 ? 4 : 8;
+    __shared__ T sx[2][5][256 + 2 * R];   // x split fluxes of the current row, halo copies at both ends
+    __shared__ T sF[5][256];              // x face fluxes F(x + 1/2) of the current row
+    __shared__ T lxr[D][5][256];          // x part of L of the last rows, by row mod D
+    const int nx = A.n[0], ny = A.n[1];
+    const int x = threadIdx.x, w = blockIdx.x;
+    const int k0 = blockIdx.y * A.seg;
+    const int kend = min(k0 + A.seg, ny);
+    const uint32_t sb = (uint32_t)sizeof(T) * (uint32_t)nx;
+    const uint32_t cb = (uint32_t)sizeof(T) * ((uint32_t)x + (uint32_t)nx * (uint32_t)ny * (uint32_t)w);
+    const long long F = A.fstride;
+    const T eps2 = (T)4 * A.eps;   // doubled split fluxes
+    const T hinv = (T)0.5 * A.inv_h;
+    const T hx = (T)0.5 * inv_hx;
+    const int xl = x == 0 ? nx - 1 : x - 1;
+    unsigned clamped = 0;
+
+    auto fetch = [&](int m, T u[5]) {
+        if (m >= 0 && m < ny) {
+            const uint32_t off = cb + (uint32_t)m * sb;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) u[f] = ld_off(A.us + f * F, off);
+        } else {
+            load_cell<T, 1>(A, x, m, w, u);
+        }
+    };
+    // recovery of row m's cell for both axes; y split fluxes out, and the x
+    // part of L of row m into the ring when the row is owned (uniform per block)
+    auto enter = [&](int m, const T u[5], T fp[5], T fm[5]) {
+        double kap, Mxs, Mys, p;
+        recover_kp((double)u[0], (double)u[1], (double)u[2], (double)u[3], kap, Mxs, Mys, p, clamped);
+        split_flux_vp<T, 1>(u, (T)(kap * Mys), (T)p, fp, fm);
+        if (m < k0 || m >= kend) return;
+        T fpx[5], fmx[5];
+        split_flux_vp<T, 0>(u, (T)(kap * Mxs), (T)p, fpx, fmx);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            sx[0][c][x + R] = fpx[c];
+            sx[1][c][x + R] = fmx[c];
+            if (x < R) {
+                sx[0][c][x + nx + R] = fpx[c];
+                sx[1][c][x + nx + R] = fmx[c];
+            }
+            if (x >= nx - R) {
+                sx[0][c][x - nx + R] = fpx[c];
+                sx[1][c][x - nx + R] = fmx[c];
+            }
+        }
+        __syncthreads();
+        T Fr[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            // window of face x + 1/2: cells x - R + 1 .. x + R at LDS positions x + 1 ..
+            Fr[c] = recon_plus<T, ORDER>(&sx[0][c][x + 1], eps2) + recon_minus<T, ORDER>(&sx[1][c][x + 1], eps2);
+            sF[c][x] = Fr[c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 5; ++c) lxr[m & (D - 1)][c][x] = (sF[c][xl] - Fr[c]) * hx;
+    };
+
+    // y window of interface k-1/2: cells k-R .. k+R-1
+    T wp[5][W], wm[5][W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        T u[5], fp[5], fm[5];
+        fetch(k0 - R + j, u);
+        enter(k0 - R + j, u, fp, fm);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            wp[c][j] = fp[c];
+            wm[c][j] = fm[c];
+        }
+    }
+    T Fl[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        Fl[c] = recon_plus<T, ORDER>(wp[c], eps2) + recon_minus<T, ORDER>(wm[c], eps2);
+
+    T nxt[5];
+    fetch(k0 + R, nxt);
+    for (int k = k0; k < kend; ++k) {
+        T u[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f] = nxt[f];
+        fetch(k + 1 + R, nxt);
+        const uint32_t off = cb + (uint32_t)k * sb;
+        T fp[5], fm[5];
+        enter(k + R, u, fp, fm);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+#pragma unroll
+            for (int j = 0; j < W - 1; ++j) {
+                wp[c][j] = wp[c][j + 1];
+                wm[c][j] = wm[c][j + 1];
+            }
+            wp[c][W - 1] = fp[c];
+            wm[c][W - 1] = fm[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T Fr = recon_plus<T, ORDER>(wp[c], eps2) + recon_minus<T, ORDER>(wm[c], eps2);
+            const T Lk = (Fl[c] - Fr) * hinv;
+            Fl[c] = Fr;
+            const T L = lxr[k & (D - 1)][c][x] + Lk;
+            T v;
+            if (A.stage == STAGE_WRITE_L) {
+                v = L;
+            } else {
+                v = ld_off(A.us + c * F, off) + A.dt * L;
+                if (A.stage == STAGE_2) v = (T)0.75 * ld_off(A.u0 + c * F, off) + (T)0.25 * v;
+                else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * ld_off(A.u0 + c * F, off) + (T)(2.0 / 3.0) * v;
+            }
+            st_off(A.stage == STAGE_WRITE_L ? A.lacc + c * F : A.uout + c * F, off, v);
+        }
+    }
+    if (clamped) atomicAdd(A.clamps, clamped);
+}
+
+bool sweep_xy_applies(int order, const int n[3], int bc_x) {
+    static const bool off = [] {
+        const char* e = getenv("RH_FUSE_XY");
+        return e && e[0] == '0';
+    }();
+    return !off && order == 5 && bc_x == RH_BC_PERIODIC && n[0] % 64 == 0 && n[0] >= 64 && n[0] <= 256 &&
+           n[1] > 1;
+}
+
+template <class T>
+hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s) {
+    if (order != 5 || a.n[0] % 64 != 0 || a.n[0] < 64 || a.n[0] > 256) return hipErrorInvalidValue;
+    const int seg = choose_segment(a.n[1], a.n[0] * a.n[2]);
+    a.seg = seg;
+    const unsigned gy = (a.n[1] + seg - 1) / seg;
+    sweep_xy<T, 5><<<dim3((unsigned)a.n[2], gy), dim3((unsigned)a.n[0]), 0, s>>>(a, inv_hx);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_sweep(int dir, int order, const SweepArgs<T>& a, hipStream_t s) {
     if (order == 5) {
@@ -707,7 +859,8 @@ hipError_t launch_totals(const T* state, long long n, double* partials, int nblk
     template hipError_t launch_get_fields<T>(const T*, double*, int, long long, unsigned*,         \
                                              hipStream_t);                                         \
     template hipError_t launch_totals<T>(const T*, long long, double*, int, double*, hipStream_t); \
-    template hipError_t launch_sweep_batch<T>(int, int, int, const BatchArgs<T>&, int, hipStream_t);
+    template hipError_t launch_sweep_batch<T>(int, int, int, const BatchArgs<T>&, int, hipStream_t); \
+    template hipError_t launch_sweep_xy<T>(int, SweepArgs<T>, T, hipStream_t);
 
 RH_INSTANTIATE(float)
 RH_INSTANTIATE(double)

@@ -19,8 +19,9 @@ RH_PREC_FP64, RH_PREC_FP32 = 0, 1
 RH_BC_PERIODIC, RH_BC_OUTFLOW, RH_BC_HUBBLE = 0, 1, 2
 RH_FIELDS_CONSERVED, RH_FIELDS_PRIMITIVE = 0, 1
 RH_KERNEL_SWEEP_X, RH_KERNEL_SWEEP_Y, RH_KERNEL_SWEEP_Z, RH_KERNEL_OTHER, RH_KERNEL_ADJOINT = 0, 1, 2, 3, 4
-RH_KERNEL_CLASSES = 5
-KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint")
+RH_KERNEL_SWEEP_XY = 5
+RH_KERNEL_CLASSES = 6
+KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint", "sweep_xy")
 
 
 class rh_grid_desc(ctypes.Structure):

@@ -67,6 +67,20 @@ def test_profile_gated_on_hash_and_scheme(tmp_path, monkeypatch):
     assert bench.load_traffic("sweep_z", "fp32", 5) is None
 
 
+def test_roofline_of_the_fused_sweep(monkeypatch):
+    monkeypatch.setattr(bench, "load_profile", lambda precision, order=5: {})
+    n = 256 ** 3
+    run = {"kernels": {"sweep_x": (0.0, 0), "sweep_y": (0.0, 0), "sweep_xy": (18.0, 60),
+                       "sweep_z": (15.0, 60)}, "ms_per_step": 2.0}
+    dom, roof, hbm = bench.roofline(run, "fp32", 5, n)
+    assert dom == "sweep_xy"
+    # two directional sweeps per launch; reads u and writes L (10 values per cell)
+    assert roof["flops_per_cell"] == 2 * bench.sweep_flops_per_cell(5)
+    assert roof["achieved"] == pytest.approx(2 * bench.sweep_flops_per_cell(5) * n / (18.0 / 60 * 1e-3) / 1e12,
+                                             rel=1e-3)
+    assert hbm["design_bytes_per_launch"] == 10.0 * 4 * n
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
