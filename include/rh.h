@@ -67,8 +67,9 @@ typedef int rh_status;
 #define RH_KERNEL_SWEEP_Z 2   /* z-direction WENO sweep */
 #define RH_KERNEL_OTHER   3   /* combine, conversion and reduction kernels */
 #define RH_KERNEL_ADJOINT 4   /* adjoint sweeps (all axes) */
-#define RH_KERNEL_SWEEP_XY 5  /* fused x and y sweep (WENO5, periodic x of 64..256 cells, a
-                                 multiple of 64): one launch in place of the x and y sweeps */
+#define RH_KERNEL_SWEEP_XY 5  /* fused x and y sweep (WENO5, and WENO7 in FP32; periodic x of
+                                 64..256 cells, a multiple of 64): one launch in place of the x
+                                 and y sweeps */
 #define RH_KERNEL_CLASSES 6
 
 typedef struct rh_grid_desc {

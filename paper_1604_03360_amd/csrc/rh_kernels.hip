@@ -617,7 +617,8 @@ static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused x and y sweeps (periodic x, nx a multiple of 64 up to 256, WENO5)
+// Fused x and y sweeps (periodic x, nx a multiple of 64 up to 256; WENO5, and
+// WENO7 in FP32)
 // ---------------------------------------------------------------------------
 // A block holds whole x rows (lane = x) of one z plane and rolls along a y
 // segment like sweep_roll_body.  Each row that enters the y window is
@@ -630,10 +631,11 @@ static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
 template <class T, int ORDER>
 __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_xy(SweepArgs<T> A, T inv_hx) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R;
-    constexpr int D = R + 1 <= 4 ? 4 : 8;
+    constexpr int D = R + 1;              // rows whose x part of L is pending
     __shared__ T sx[2][5][256 + 2 * R];   // x split fluxes of the current row, halo copies at both ends
     __shared__ T sF[5][256];              // x face fluxes F(x + 1/2) of the current row
-    __shared__ T lxr[D][5][256];          // x part of L of the last rows, by row mod D
+    __shared__ T lxr[D][5][256];          // x part of L of the last rows, by row mod D (rows are
+                                          // uniform across the block: scalar index arithmetic)
     const int nx = A.n[0], ny = A.n[1];
     const int x = threadIdx.x, w = blockIdx.x;
     const int k0 = blockIdx.y * A.seg;
@@ -687,8 +689,9 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
             sF[c][x] = Fr[c];
         }
         __syncthreads();
+        const int slot = m % D;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) lxr[m & (D - 1)][c][x] = (sF[c][xl] - Fr[c]) * hx;
+        for (int c = 0; c < 5; ++c) lxr[slot][c][x] = (sF[c][xl] - Fr[c]) * hx;
     };
 
     // y window of interface k-1/2: cells k-R .. k+R-1
@@ -729,12 +732,13 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
             wp[c][W - 1] = fp[c];
             wm[c][W - 1] = fm[c];
         }
+        const int slot = k % D;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             const T Fr = recon_plus<T, ORDER>(wp[c], eps2) + recon_minus<T, ORDER>(wm[c], eps2);
             const T Lk = (Fl[c] - Fr) * hinv;
             Fl[c] = Fr;
-            const T L = lxr[k & (D - 1)][c][x] + Lk;
+            const T L = lxr[slot][c][x] + Lk;
             T v;
             if (A.stage == STAGE_WRITE_L) {
                 v = L;
@@ -749,22 +753,31 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
     if (clamped) atomicAdd(A.clamps, clamped);
 }
 
-bool sweep_xy_applies(int order, const int n[3], int bc_x) {
+// RH_FUSE_XY=0 in the environment selects the separate sweeps everywhere (the
+// results are bitwise the same; used to compare the two paths).
+bool sweep_xy_applies(int order, bool fp32, const int n[3], int bc_x) {
     static const bool off = [] {
         const char* e = getenv("RH_FUSE_XY");
         return e && e[0] == '0';
     }();
-    return !off && order == 5 && bc_x == RH_BC_PERIODIC && n[0] % 64 == 0 && n[0] >= 64 && n[0] <= 256 &&
-           n[1] > 1;
+    return !off && (order == 5 || (order == 7 && fp32)) && bc_x == RH_BC_PERIODIC && n[0] % 64 == 0 &&
+           n[0] >= 64 && n[0] <= 256 && n[1] > 1;
 }
 
 template <class T>
 hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s) {
-    if (order != 5 || a.n[0] % 64 != 0 || a.n[0] < 64 || a.n[0] > 256) return hipErrorInvalidValue;
+    if (!(order == 5 || (order == 7 && sizeof(T) == 4)) || a.n[0] % 64 != 0 || a.n[0] < 64 || a.n[0] > 256)
+        return hipErrorInvalidValue;
     const int seg = choose_segment(a.n[1], a.n[0] * a.n[2]);
     a.seg = seg;
     const unsigned gy = (a.n[1] + seg - 1) / seg;
-    sweep_xy<T, 5><<<dim3((unsigned)a.n[2], gy), dim3((unsigned)a.n[0]), 0, s>>>(a, inv_hx);
+    const dim3 grid((unsigned)a.n[2], gy), block((unsigned)a.n[0]);
+    if (order == 5) {
+        sweep_xy<T, 5><<<grid, block, 0, s>>>(a, inv_hx);
+    } else if constexpr (sizeof(T) == 4) {
+        // FP64 WENO7 would need 82 KB of LDS per block (one block per CU): split sweeps
+        sweep_xy<T, 7><<<grid, block, 0, s>>>(a, inv_hx);
+    }
     return hipGetLastError();
 }
 

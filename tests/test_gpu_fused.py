@@ -1,7 +1,8 @@
-"""The fused x-y sweep (WENO5 grids with a periodic x axis of 64..256 cells, a
-multiple of 64) against the FP64 oracle: non-periodic and analytic y
-boundaries, a grid with one z plane (the fused launch then applies the stage
-combine), every admissible row length, FP64 (1e-12) and FP32 (2e-5)."""
+"""The fused x-y sweep (WENO5 grids, and FP32 WENO7 grids, with a periodic x
+axis of 64..256 cells, a multiple of 64) against the FP64 oracle: non-periodic
+and analytic y boundaries, a grid with one z plane (the fused launch then
+applies the stage combine), every admissible row length, FP64 (1e-12) and FP32
+(2e-5); graph replays; bitwise equality with the separate sweeps."""
 import numpy as np
 import pytest
 
@@ -13,34 +14,34 @@ pytestmark = pytest.mark.gpu
 P, O, H = inputs.BC_PERIODIC, inputs.BC_OUTFLOW, inputs.BC_HUBBLE
 
 
-def hubble_periodic_x():
-    spec = inputs.hubble(n=64, order=5, half_width=3.0)
+def hubble_periodic_x(o=5):
+    spec = inputs.hubble(n=64, order=o, half_width=3.0)
     spec["bc"] = (P, H, H)
     return spec
 
 
 CASES = {
-    "outflow_yz": lambda: inputs.random_smooth((64, 27, 13), h=0.1, seed=81, bc=(P, O, O)),
-    "one_z_plane": lambda: inputs.random_smooth((128, 20, 1), h=0.1, seed=82),
-    "rows_of_192": lambda: inputs.random_smooth((192, 17, 5), h=0.05, seed=83, bc=(P, P, O)),
-    "rows_of_256": lambda: inputs.random_smooth((256, 9, 3), h=0.05, seed=84),
+    "outflow_yz": lambda o=5: inputs.random_smooth((64, 27, 13), h=0.1, seed=81, bc=(P, O, O), order=o),
+    "one_z_plane": lambda o=5: inputs.random_smooth((128, 20, 1), h=0.1, seed=82, order=o),
+    "rows_of_192": lambda o=5: inputs.random_smooth((192, 17, 5), h=0.05, seed=83, bc=(P, P, O), order=o),
+    "rows_of_256": lambda o=5: inputs.random_smooth((256, 9, 3), h=0.05, seed=84, order=o),
     "hubble_y": hubble_periodic_x,
 }
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
-def test_fused_xy_matches_oracle(case, precision, tol):
+@pytest.mark.parametrize("precision,tol,order", [("fp64", 1e-12, 5), ("fp32", 2e-5, 5), ("fp32", 2e-5, 7)])
+def test_fused_xy_matches_oracle(case, precision, tol, order):
     rh = rh_module()
-    spec = CASES[case]()
+    spec = CASES[case](order)
     assert spec["shape"][0] % 64 == 0 and spec["bc"][0] == P
     prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
     nsteps = 3
     got, tg, _, cnt = gpu_steps(spec, prec, nsteps)
     ref, tr = oracle_steps(spec, nsteps)
     assert tg == pytest.approx(tr, abs=1e-12)
-    print(case, precision, field_errors(got, ref), flush=True)
-    assert_fields_close(got, ref, tol, "%s %s" % (case, precision))
+    print(case, precision, order, field_errors(got, ref), flush=True)
+    assert_fields_close(got, ref, tol, "%s %s WENO%d" % (case, precision, order))
     assert cnt[1] == 0
 
 
@@ -75,10 +76,11 @@ sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
 from paper_1604_03360_amd import inputs
 from gpu_helpers import gpu_steps, rh_module
 rh = rh_module()
-spec = inputs.random_smooth((128, 27, 11), h=0.1, seed=85, bc=(0, 1, 0))
-for name, prec in (("fp64", rh.RH_PREC_FP64), ("fp32", rh.RH_PREC_FP32)):
-    got, _, _, _ = gpu_steps(spec, prec, 3)
-    np.save(sys.argv[2] + "_" + name + ".npy", got)
+for o in (5, 7):
+    spec = inputs.random_smooth((128, 27, 11), h=0.1, seed=85, bc=(0, 1, 0), order=o)
+    for name, prec in (("fp64", rh.RH_PREC_FP64), ("fp32", rh.RH_PREC_FP32)):
+        got, _, _, _ = gpu_steps(spec, prec, 3)
+        np.save("%s_%s_%d.npy" % (sys.argv[2], name, o), got)
 """
 
 
@@ -95,8 +97,9 @@ def test_fused_xy_is_bitwise_the_split_sweeps(tmp_path):
                        text=True, timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
     rh = rh_module()
-    spec = inputs.random_smooth((128, 27, 11), h=0.1, seed=85, bc=(P, O, P))
-    for name, prec in (("fp64", rh.RH_PREC_FP64), ("fp32", rh.RH_PREC_FP32)):
-        got, _, _, _ = gpu_steps(spec, prec, 3)
-        split = np.load(out + "_" + name + ".npy")
-        assert np.array_equal(got, split), (name, np.abs(got - split).max())
+    for o in (5, 7):
+        spec = inputs.random_smooth((128, 27, 11), h=0.1, seed=85, bc=(P, O, P), order=o)
+        for name, prec in (("fp64", rh.RH_PREC_FP64), ("fp32", rh.RH_PREC_FP32)):
+            got, _, _, _ = gpu_steps(spec, prec, 3)
+            split = np.load("%s_%s_%d.npy" % (out, name, o))
+            assert np.array_equal(got, split), (name, o, np.abs(got - split).max())
