@@ -685,6 +685,185 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// x axis of a periodic grid whose rows hold NX = 32 .. 256 cells: a block of
+// (256 / NX) x NX lanes takes whole rows, one cell per lane.  The lane stages
+// its own cell's split fluxes and weight (the periodic ghosts are extra LDS
+// copies written by the cells they copy), differentiates the face to its right
+// and gathers the partials of the faces that reach its cell.  No lane stages a
+// ghost from HBM or differentiates a halo face, which the tiled kernel does for
+// 2R - 1 faces per row (a fifth of its face rounds at 64 x 4).  The arithmetic
+// and the order of every sum are those of adj_x, so both give the same bits.
+// ---------------------------------------------------------------------------
+template <class T, int ORDER, int NX>
+__global__ void __launch_bounds__(256) adj_xrow(AdjArgs<T> A, Lin3<T> init) {
+    constexpr int R = (ORDER + 1) / 2, K = 2 * R - 1;
+    constexpr int RPB = 256 / NX;        // rows per block
+    constexpr int NP = NX + 2 * R - 1;   // padded row: cells -(R-1) .. NX+R-1 at p = cell + R - 1
+    static_assert(NX >= 2 * R && RPB >= 1, "row longer than the stencil");
+    __shared__ T sfp[5][RPB][NP];
+    __shared__ T sfm[5][RPB][NP];
+    __shared__ T sw[5][RPB][NX];
+    __shared__ T sp[RPB][NX][K];         // plus partials of face x for cells x-R+1 .. x+R-1
+    __shared__ T sm[RPB][NX][K];         // minus partials of face x for cells x-R+2 .. x+R
+    const int tid = threadIdx.x;
+    const int ly = tid / NX, x = tid - ly * NX;
+    const long long row = (long long)blockIdx.x * RPB + ly;
+    const bool live = row < (long long)A.n[1] * A.n[2];
+    const long long id = x + (long long)NX * row;
+    const T half = (T)0.5;
+
+    T uf[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+    T kap = (T)0, kE = (T)0, kM2 = (T)0, pE = (T)0, pM2 = (T)0;
+    {
+        T fp[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, fm[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+        T w5[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+        if (live) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                uf[f] = A.u[f * A.fstride + id];
+                w5[f] = A.w[f * A.fstride + id];
+            }
+            // the recovery pack of the lane's cell (as adj_pack computes it),
+            // also stored for the y and z sweeps
+            const RecoveryPack o = recovery_pack((double)uf[0], (double)uf[1], (double)uf[2], (double)uf[3]);
+            kap = (T)o.kap;
+            const T P = (T)o.p;
+            kE = (T)o.kap_E;
+            kM2 = (T)o.kap_M2;
+            pE = (T)o.p_E;
+            pM2 = (T)o.p_M2;
+            A.pk[id] = kap;
+            A.pk[A.fstride + id] = P;
+            A.pk[2 * A.fstride + id] = kE;
+            A.pk[3 * A.fstride + id] = kM2;
+            A.pk[4 * A.fstride + id] = pE;
+            A.pk[5 * A.fstride + id] = pM2;
+            const T v = kap * uf[1];
+            T f[5];
+            f[0] = uf[1];
+            f[1] = uf[1] * v + P;
+            f[2] = uf[2] * v;
+            f[3] = uf[3] * v;
+            f[4] = uf[4] * v;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                fp[c] = f[c] + uf[c];   // doubled split fluxes (eps scaled by 4 below)
+                fm[c] = f[c] - uf[c];
+            }
+        }
+        const int p = x + R - 1;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            sfp[c][ly][p] = fp[c];
+            sfm[c][ly][p] = fm[c];
+            sw[c][ly][x] = w5[c];
+        }
+        if (x >= NX - (R - 1)) {   // left ghosts -(R-1) .. -1
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                sfp[c][ly][p - NX] = fp[c];
+                sfm[c][ly][p - NX] = fm[c];
+            }
+        }
+        if (x < R) {               // right ghosts NX .. NX+R-1
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                sfp[c][ly][p + NX] = fp[c];
+                sfm[c][ly][p + NX] = fm[c];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int xr = x + 1 < NX ? x + 1 : 0;
+    T ap[5], am[5];
+#pragma unroll 1
+    for (int c = 0; c < 5; ++c) {
+        {
+            // face x (between cells x and x+1); its plus stencil starts at p = x
+            T op[K], om[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) op[k] = om[k] = (T)0;
+            const T g = (sw[c][ly][xr] - sw[c][ly][x]) * A.inv_h;
+            if constexpr (ORDER == 5) {
+                weno5_grad_acc_e<T>(sfp[c][ly][x], sfp[c][ly][x + 1], sfp[c][ly][x + 2], sfp[c][ly][x + 3],
+                                    sfp[c][ly][x + 4], (T)16 * A.eps, g, op[0], op[1], op[2], op[3], op[4]);
+                weno5_grad_acc_e<T>(sfm[c][ly][x + 5], sfm[c][ly][x + 4], sfm[c][ly][x + 3], sfm[c][ly][x + 2],
+                                    sfm[c][ly][x + 1], (T)16 * A.eps, g, om[4], om[3], om[2], om[1], om[0]);
+            } else {
+                T sv[7], o[7];
+#pragma unroll
+                for (int j = 0; j < 7; ++j) {
+                    sv[j] = sfp[c][ly][x + j];
+                    o[j] = (T)0;
+                }
+                weno7_grad_acc<T>(sv, (T)4 * A.eps, g, o);
+#pragma unroll
+                for (int j = 0; j < 7; ++j) op[j] = o[j];
+#pragma unroll
+                for (int j = 0; j < 7; ++j) {
+                    sv[j] = sfm[c][ly][x + 7 - j];
+                    o[j] = (T)0;
+                }
+                weno7_grad_acc<T>(sv, (T)4 * A.eps, g, o);
+#pragma unroll
+                for (int j = 0; j < 7; ++j) om[6 - j] = o[j];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                sp[ly][x][k] = op[k];
+                sm[ly][x][k] = om[k];
+            }
+        }
+        __syncthreads();
+        // partials reaching cell x: plus from faces x+R-1-k, minus from faces x+R-2-k
+        T a_p = (T)0, a_m = (T)0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int fp_ = x + R - 1 - k, fm_ = x + R - 2 - k;
+            fp_ = fp_ < 0 ? fp_ + NX : (fp_ >= NX ? fp_ - NX : fp_);
+            fm_ = fm_ < 0 ? fm_ + NX : (fm_ >= NX ? fm_ - NX : fm_);
+            a_p += sp[ly][fp_][k];
+            a_m += sm[ly][fm_][k];
+        }
+        ap[c] = a_p;
+        am[c] = a_m;
+        __syncthreads();
+    }
+    if (!live) return;
+    T lam[5], g[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        lam[c] = half * (ap[c] + am[c]);
+        g[c] = half * (ap[c] - am[c]);
+    }
+    // F = (Mx, Mx v + p, My v, Mz v, N v) with v = kappa Mx
+    const T Mx = uf[1], vd = kap * Mx;
+    g[1] += lam[0];
+    T S = (T)0;
+#pragma unroll
+    for (int c = 1; c < 5; ++c) {
+        S += lam[c] * uf[c];
+        g[c] += lam[c] * vd;
+    }
+    const T lp = lam[1];
+    g[0] += S * (Mx * kE) + lp * pE;
+    const T sk = (T)2 * S * Mx * kM2, spp = (T)2 * lp * pM2;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) g[1 + m] += (sk + spp) * uf[1 + m];
+    g[1] += S * kap;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        const long long o = f * A.fstride + id;
+        T acc = (T)0;
+        if (init.X1) acc += init.a1 * init.X1[o];
+        if (init.X2) acc += init.a2 * init.X2[o];
+        if (init.X3) acc += init.a3 * init.X3[o];
+        A.ub[o] = acc + A.scale * g[f];
+    }
+}
+
 // Tile of the x adjoint: the narrowest of 64, 32, 16 cells that wastes the
 // least on a ragged row end (2R - 1 halo faces per row).  A 128 x 4 tile with
 // two cells per lane halves the idle lanes of the last face round but needs
@@ -754,9 +933,44 @@ hipError_t launch_adjoint_sweep(int dir, int order, AdjArgs<T> a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Whole-row x adjoint for periodic rows of these lengths (RH_ADJ_XROW=0 keeps
+// the tiled kernel and the separate pack launch, for comparisons).
+bool adjoint_x_rows(const int n[3], int bc_x) {
+    static const bool enabled = [] {
+        const char* e = getenv("RH_ADJ_XROW");
+        return !(e && e[0] == '0');
+    }();
+    const int nx = n[0];
+    return enabled && bc_x == RH_BC_PERIODIC &&
+           (nx == 32 || nx == 64 || nx == 96 || nx == 128 || nx == 192 || nx == 256);
+}
+
+template <class T, int ORDER>
+static void launch_adjoint_rows(const AdjArgs<T>& a, const Lin3<T>& init, hipStream_t s) {
+    const int nx = a.n[0];
+    const long long nrows = (long long)a.n[1] * a.n[2];
+    auto go = [&](auto kernel, int nxk) {
+        const int rpb = 256 / nxk;
+        kernel<<<dim3((unsigned)((nrows + rpb - 1) / rpb)), dim3(rpb * nxk), 0, s>>>(a, init);
+    };
+    switch (nx) {
+        case 32: go(adj_xrow<T, ORDER, 32>, 32); break;
+        case 64: go(adj_xrow<T, ORDER, 64>, 64); break;
+        case 96: go(adj_xrow<T, ORDER, 96>, 96); break;
+        case 128: go(adj_xrow<T, ORDER, 128>, 128); break;
+        case 192: go(adj_xrow<T, ORDER, 192>, 192); break;
+        default: go(adj_xrow<T, ORDER, 256>, 256); break;
+    }
+}
+
 template <class T>
 hipError_t launch_adjoint_x(int order, AdjArgs<T> a, Lin3<T> init, hipStream_t s) {
     if (!a.pk) return hipErrorInvalidValue;
+    if (adjoint_x_rows(a.n, a.bc)) {
+        if (order == 5) launch_adjoint_rows<T, 5>(a, init, s);
+        else launch_adjoint_rows<T, 7>(a, init, s);
+        return hipGetLastError();
+    }
     const int tx = adjoint_tile_x(a.n[0]);
     const int ty = tx == 64 ? 4 : 256 / tx;
     const long long ntx = (a.n[0] + tx - 1) / tx;

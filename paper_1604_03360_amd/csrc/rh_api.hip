@@ -1020,9 +1020,10 @@ rh_status rh_batch_kernel_times(rh_batch* b, double* ms_out, long long* launches
 namespace {
 
 // out = (a1 X1 + a2 X2 + a3 X3) + s J(u)^T w (null X terms are skipped; they may
-// alias out).  The recovery pack of u (six fields) goes to the bound workspace;
-// the x-axis kernel writes out from the linear combination and its own part,
-// the y and z sweeps add theirs.
+// alias out).  The recovery pack of u (six fields) goes to the bound workspace,
+// from its own launch or from the whole-row x kernel; the x-axis kernel writes
+// out from the linear combination and its own part, the y and z sweeps add
+// theirs.
 template <class T>
 rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, rh::Lin3<T> init, T s) {
     const long long N = 5 * p->ncell;
@@ -1051,10 +1052,14 @@ rh_status vjp_impl(rh_plan* p, double t, const T* u, const T* w, T* out, rh::Lin
     base.hb.h[0] = h[0];
     base.hb.h[1] = h[1];
     base.hb.h[2] = h[2];
-    rh_status st = timed_launch(p, RH_KERNEL_OTHER,
-                                [&] { return rh::launch_adjoint_pack<T>(u, pk, p->ncell, p->stream); },
-                                "pack launch");
-    if (st != RH_OK) return st;
+    // the whole-row x adjoint computes the pack of its cells and stores it
+    const bool x_packs = n[0] > 1 && rh::adjoint_x_rows(n, p->d.bc[0]);
+    rh_status st = RH_OK;
+    if (!x_packs) {
+        st = timed_launch(p, RH_KERNEL_OTHER,
+                          [&] { return rh::launch_adjoint_pack<T>(u, pk, p->ncell, p->stream); }, "pack launch");
+        if (st != RH_OK) return st;
+    }
     if (n[0] > 1) {
         rh::AdjArgs<T> x = base;
         x.bc = p->d.bc[0];

@@ -66,7 +66,8 @@ struct AdjArgs {
     T inv_h;
     T eps;
     T scale;            // ub += scale * (J^T w) of this axis
-    const T* pk;        // per-cell recovery pack (kappa, p, dkappa/dE, dkappa/dM2, dp/dE, dp/dM2) or null
+    T* pk;              // per-cell recovery pack (kappa, p, dkappa/dE, dkappa/dM2, dp/dE, dp/dM2) or null;
+                        // the whole-row x adjoint writes it, the other sweeps read it
     HubbleBC hb;
 };
 
@@ -85,10 +86,13 @@ struct Lin3 {
     T a1, a2, a3;
     const T *X1, *X2, *X3;
 };
-// x axis of the adjoint (LDS tiles): a.ub = init + a.scale J_x^T w, written
-// without reading a.ub.  a.pk (required) holds the recovery pack.
+// x axis of the adjoint (LDS tiles or whole rows): a.ub = init + a.scale J_x^T w,
+// written without reading a.ub.  a.pk (required) holds the recovery pack, or,
+// where adjoint_x_rows() holds, receives it from this launch (whole-row kernel).
 template <class T>
 hipError_t launch_adjoint_x(int order, AdjArgs<T> a, Lin3<T> init, hipStream_t s);
+// True where the x adjoint takes whole periodic rows and writes the pack itself.
+bool adjoint_x_rows(const int n[3], int bc_x);
 template <class T>
 hipError_t launch_fill_zero(T* p, long long n, hipStream_t s);
 template <class T>
