@@ -134,3 +134,71 @@ def test_blob_64_full_length():
     assert np.all(err64 <= 1e-12), err64
     assert np.all(err32 <= 1e-4), err32
     assert cnt == [0, 0] and cnt32[1] == 0
+
+
+def test_blob_256_adjoint_against_oracle(blob_specs, blob_oracle):
+    """J(u)^T w at 256^3 in the launch configuration the benchmark's adjoint leg
+    times (whole-row x kernel over 256-cell rows, y and z sweeps in 32-cell
+    segments), at the blob's state after one step (the oracle's), against the
+    oracle's adjoint, normalised by max(max|ref|, max|w|/h): FP64 to 1e-12; FP32
+    on the FP32-rounded inputs to four times the problem's own sensitivity to
+    FP32 rounding (the oracle's change when u moves by a random half FP32 ulp:
+    about 9e-5 at this state, where e spans 1e-3 to 20 and the WENO weight
+    derivatives amplify it), and never looser than needed below 5e-5.  Then the
+    adjoint of one FP32 step from stored stages (the timed call) equals the
+    recomputing one bitwise and the FP64 one on the same rounded inputs to the
+    same bar."""
+    import torch
+    rh = rh_module()
+    spec = blob_specs[5]
+    g = oracle.grid_from_spec(spec)
+    u = blob_oracle(5)
+    w = np.random.default_rng(256).normal(size=u.shape)
+    t, dt, h = spec["t0"] + spec["dt"], spec["dt"], min(spec["h"])
+
+    def errs(got, ref, ww):
+        got = np.asarray(got, np.float64).reshape(5, -1)
+        ref = ref.reshape(5, -1)
+        return np.abs(got - ref).max(axis=1) / max(np.abs(ref).max(), np.abs(ww).max() / h)
+
+    print("blob 256^3 adjoint fp64", flush=True)
+    h64 = rh.Hydro.from_spec(spec, precision=rh.RH_PREC_FP64)
+    got = h64.vjp(u, w, t=t).cpu().numpy()
+    err = errs(got, oracle.vjp_L(g, u, w, t=t), w)
+    print("fp64", err, flush=True)
+    assert np.all(err <= 1e-12), err
+    del got
+
+    print("blob 256^3 adjoint fp32", flush=True)
+    u32 = u.astype(np.float32).astype(np.float64)
+    w32 = w.astype(np.float32).astype(np.float64)
+    ref32 = oracle.vjp_L(g, u32, w32, t=t)
+    up = u32 * (1.0 + 2.0 ** -24 * np.random.default_rng(257).uniform(-1.0, 1.0, size=u.shape))
+    sens = errs(oracle.vjp_L(g, up, w32, t=t), ref32, w32).max()
+    del up
+    bar = max(5e-5, 4.0 * sens)
+    h32 = rh.Hydro.from_spec(spec, precision=rh.RH_PREC_FP32)
+    got = h32.vjp(u32, w32, t=t).double().cpu().numpy()
+    err = errs(got, ref32, w32)
+    print("fp32", err, "sensitivity to a half-ulp change of u %.3e, bar %.3e" % (sens, bar), flush=True)
+    assert sens < 1e-3, sens
+    assert np.all(err <= bar), err
+    del got, ref32
+
+    print("blob 256^3 step adjoint from stored stages", flush=True)
+    un = torch.as_tensor(u32, device="cuda").float()
+    wb = torch.as_tensor(w32, device="cuda").float()
+    h32.state.copy_(un)
+    h32.t = t
+    stages = h32.step_store(dt)
+    stored = h32.step_vjp_stored(un, stages, wb, dt, t=t).double().cpu().numpy()
+    del stages
+    recomputed = h32.step_vjp(un, wb, dt, t=t).double().cpu().numpy()
+    assert np.array_equal(stored, recomputed)
+    del recomputed
+    ref = h64.step_vjp(u32, w32, dt, t=t).cpu().numpy()
+    h32.close()
+    h64.close()
+    err = np.abs(stored - ref).reshape(5, -1).max(axis=1) / np.abs(ref).max()
+    print("fp32 stored-stage step adjoint vs fp64", err, flush=True)
+    assert np.all(err <= bar), err
