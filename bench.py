@@ -123,10 +123,15 @@ def run_gpu(spec, precision, steps, warmup):
             "kernels": ktimes, "totals": tot, "counters": cnt}
 
 
-def run_adjoint(spec, precision, reps):
+def run_adjoint(spec, precision, reps, repeats=5):
     """Time the adjoint of one SSP-RK3 step with its stage states resident in HBM
     (recorded by rh_step_store), the same adjoint with the stage states
-    recomputed (rh_step_vjp), and one forward step, all on the same plan."""
+    recomputed (rh_step_vjp), and one forward step, all on the same plan with
+    eager launches and no per-launch timing events: each figure is the median
+    over `repeats` runs of `reps` calls.  The per-kernel adjoint times come from
+    a separate pass with the library's per-launch events on."""
+    import statistics
+
     import torch
     from paper_1604_03360_amd import rh
     prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
@@ -141,33 +146,39 @@ def run_adjoint(spec, precision, reps):
     out = h.step_vjp_stored(u_n, stages, ubar, dt, t=t_n)     # warm-up, allocates scratch
     out = h.step_vjp(u_n, ubar, dt, t=t_n)
     stream = torch.cuda.current_stream()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    torch.cuda.synchronize()
+
+    def per_call_ms(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {"stored": [], "recompute": [], "forward": []}
+    for _ in range(repeats):
+        res["stored"].append(per_call_ms(lambda: h.step_vjp_stored(u_n, stages, ubar, dt, t=t_n)))
+        res["recompute"].append(per_call_ms(lambda: h.step_vjp(u_n, ubar, dt, t=t_n)))
+        res["forward"].append(per_call_ms(lambda: h.step(dt, 1)))
+    adj_ms = statistics.median(res["stored"])
+    rec_ms = statistics.median(res["recompute"])
+    fwd_ms = statistics.median(res["forward"])
     rh.rh_set_timing(h.plan, 1)
-    e[0].record(stream)
     for _ in range(reps):
         out = h.step_vjp_stored(u_n, stages, ubar, dt, t=t_n)
-    e[1].record(stream)
-    torch.cuda.synchronize()
     kt = rh.rh_kernel_times(h.plan)
     rh.rh_set_timing(h.plan, 0)
-    e[2].record(stream)
-    for _ in range(reps):
-        out = h.step_vjp(u_n, ubar, dt, t=t_n)
-    e[3].record(stream)
-    e[4].record(stream)
-    h.step(dt, reps)
-    e[5].record(stream)
-    torch.cuda.synchronize()
-    adj_ms = e[0].elapsed_time(e[1]) / reps
-    rec_ms = e[2].elapsed_time(e[3]) / reps
-    fwd_ms = e[4].elapsed_time(e[5]) / reps
     finite = bool(torch.isfinite(out).all().item())
     h.close()
     del h, u_n, ubar, out, stages
     torch.cuda.empty_cache()
     return {"step_vjp_ms": adj_ms, "step_ms": fwd_ms, "ratio": adj_ms / fwd_ms,
             "step_vjp_recompute_ms": rec_ms, "ratio_with_recompute": rec_ms / fwd_ms, "finite": finite,
+            "ratio_range": [min(res["stored"]) / max(res["forward"]), max(res["stored"]) / min(res["forward"])],
+            "timing": "median of %d runs of %d calls each, eager launches, no per-launch events" % (repeats, reps),
             "adjoint_sweeps_ms_per_step_vjp": kt["adjoint"][0] / reps}
 
 
@@ -354,6 +365,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--scheme", type=int, default=5, choices=(5, 7))
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="timed steps of the 64-event ensemble (its configured run length)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -431,7 +444,7 @@ def main():
         return d
 
     def batch_leg():
-        b = run_batch(min(args.steps, 10), 2)
+        b = run_batch(args.batch_steps, 2)
         print("bench: batch %.4g cell-updates/s (%.3f ms/step)" % (b["value"], b["ms_per_step"]),
               file=sys.stderr, flush=True)
         return b

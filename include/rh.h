@@ -152,9 +152,14 @@ rh_status rh_step(rh_plan* plan, double dt, int n_steps, double* t_inout);
 /* Conservation diagnostics of the bound state: out[0..4] = FP64 sums of E, Mx,
  * My, Mz and N over all cells (deterministic fixed-order two-pass reduction,
  * not multiplied by the cell volume).  counters (may be NULL) receives
- * [0] = primitive recoveries that hit a floor since the plan was created or
- * last reset, [1] = cells with a non-finite conserved value.  Synchronises the
- * stream.  Errors: RH_E_STATE, RH_E_HIP, RH_E_PHYS (strict plans only). */
+ * [0] = primitive recoveries that hit a floor (E below 1e-12, or |M| at or
+ * above the velocity cap) since the plan was created or last reset, counted
+ * once per cell and evaluation of L (so one SSP-RK3 step counts a floored
+ * cell of each of its three stage inputs once) and once per cell read back by
+ * rh_get_fields(PRIMITIVE); grids with no axis longer than one cell evaluate
+ * no recovery and count nothing; [1] = cells of the bound state with a
+ * non-finite conserved value.  Synchronises the stream.
+ * Errors: RH_E_STATE, RH_E_HIP, RH_E_PHYS (strict plans only). */
 rh_status rh_totals(rh_plan* plan, double out[5], long long counters[2]);
 
 /* Replay steps from a graph (enable != 0): rh_step then captures one SSP-RK3

@@ -6,7 +6,10 @@ steps of the library's SSP-RK3 scheme and returns the final state.  The forward
 pass keeps a checkpoint of the state every ``every`` steps; the backward pass
 replays each checkpointed segment forward, keeping every step's input and its
 two Runge-Kutta stage states (``rh_step_store``), and then applies the
-hand-written adjoint of one step (``rh_step_vjp_stored``) in reverse.
+hand-written adjoint of one step (``rh_step_vjp_stored``) in reverse.  The
+replays run on the plan's own state buffer; backward restores that buffer and
+the plan's time to what they held when it was called, so stepping the plan
+after backward continues from there.
 All arithmetic runs in the library's kernels; this module only sequences calls
 and keeps the checkpoints.
 """
@@ -40,7 +43,8 @@ class HydroRun(torch.autograd.Function):
     def backward(ctx, grad_out):
         hydro, dt, every = ctx.hydro, ctx.dt, ctx.every
         ubar = grad_out.detach().to(hydro.dtype).contiguous()
-        t_end = hydro.t
+        # the replays below overwrite the plan's state: keep what it holds now
+        resume_state, resume_t = hydro.state.clone(), hydro.t
         for seg in reversed(range(len(ctx.checkpoints))):
             u_c, t_c = ctx.checkpoints[seg]
             steps = min(every, ctx.n_steps - seg * every)
@@ -53,7 +57,8 @@ class HydroRun(torch.autograd.Function):
             for j in reversed(range(steps)):
                 ubar = hydro.step_vjp_stored(states[j], stages[j], ubar, dt, t=t_c + j * dt)
             del states, stages
-        hydro.t = t_end
+        hydro.state.copy_(resume_state)
+        hydro.t = resume_t
         return ubar, None, None, None, None
 
 

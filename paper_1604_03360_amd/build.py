@@ -20,16 +20,15 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-c
          "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose=False, out=None, defines=(), objdir=None):
-    """Compile and link librh.so (or `out`), optionally with extra -D defines."""
+def build(verbose=False, out=None, objdir=None):
+    """Compile and link librh.so (or `out`)."""
     objdir = objdir or os.path.join(HERE, "_build")
     lib = out or LIB
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(HERE, "csrc", src),
-                                                                "-o", obj]
+        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

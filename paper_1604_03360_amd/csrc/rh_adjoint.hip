@@ -191,20 +191,9 @@ __device__ __forceinline__ void adj_weight(const AdjArgs<T>& A, const Column<T, 
 // (d f+/du)^T a+ + (d f-/du)^T a- to every field of the owned cells.
 //
 // Components per pass: FP32 WENO5 3 (passes {0,1,2}, {3,4}); otherwise 2.
-#ifndef RH_ADJ_GROUP_F32_W5
-#define RH_ADJ_GROUP_F32_W5 3
-#endif
-#ifndef RH_ADJ_GROUP_OTHER
-#define RH_ADJ_GROUP_OTHER 2
-#endif
-
-#ifndef RH_ADJ_ROLL_UNROLL
-#define RH_ADJ_ROLL_UNROLL 2
-#endif
-
 template <class T, int ORDER>
 struct AdjGroup {
-    static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? RH_ADJ_GROUP_F32_W5 : RH_ADJ_GROUP_OTHER;
+    static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? 3 : 2;
 };
 
 template <class T, int ORDER, int DIR, int CLO, int CHI, bool HUB>
@@ -336,7 +325,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     adj_state<T, DIR, HUB>(A, C, i_lo + R + 1, un, vn, Pn);
     // two faces per trip: the second face's window is the first one's renamed,
     // so the register moves of the shift are paid once per two faces
-#pragma unroll RH_ADJ_ROLL_UNROLL
+#pragma unroll 2
     for (int i = i_lo; i <= i_hi; ++i) {
         T wr[NC], unew[5];
 #pragma unroll
@@ -706,12 +695,9 @@ __global__ void __launch_bounds__(256) adj_x(AdjArgs<T> A, Lin3<T> init) {
 // ---------------------------------------------------------------------------
 // FP32 WENO5 rows: six waves per SIMD, the most that the LDS of 256-cell row
 // blocks allows (62 registers instead of 82; 0.5% faster at 256^3).
-#ifndef RH_ADJ_XROW_WAVES_F32_W5
-#define RH_ADJ_XROW_WAVES_F32_W5 6
-#endif
 template <class T, int ORDER>
 struct AdjRowWaves {
-    static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? RH_ADJ_XROW_WAVES_F32_W5 : 1;
+    static constexpr int value = (sizeof(T) == 4 && ORDER == 5) ? 6 : 1;
 };
 
 template <class T, int ORDER, int NX>

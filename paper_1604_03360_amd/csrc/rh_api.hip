@@ -529,6 +529,10 @@ rh_status upload_batch_table(rh_batch* b) {
         G.n[2] = d.nz;
         const double h[3] = {d.dx, d.dy, d.dz};
         const double c0[3] = {d.x0, d.y0, d.z0};
+        G.eps = (T)(d.weno_eps > 0.0 ? d.weno_eps : 1e-6);
+        G.t0 = d.hubble_t0;
+        G.e0 = d.hubble_e0;
+        G.n0 = d.hubble_n0;
         for (int a = 0; a < 3; ++a) {
             G.bc[a] = d.bc[a];
             G.inv_h[a] = (T)(1.0 / h[a]);
@@ -598,11 +602,7 @@ rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T
     B.base.lacc = lacc;
     B.base.uout = uout;
     B.base.dt = (T)dt;
-    B.base.eps = (T)(b->d[0].weno_eps > 0.0 ? b->d[0].weno_eps : 1e-6);
-    B.base.hb.t = t;
-    B.base.hb.t0 = b->d[0].hubble_t0;
-    B.base.hb.e0 = b->d[0].hubble_e0;
-    B.base.hb.n0 = b->d[0].hubble_n0;
+    B.base.hb.t = t;   // epsilon and the analytic-boundary parameters come per grid
     B.base.clamps = b->d_clamps;
     for (int d = 0; d < 3; ++d) {
         rh::BatchArgs<T> Bd = B;
@@ -916,7 +916,6 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
                 B.base.us = (const float*)b->state;
                 B.base.u0 = (const float*)b->state;
                 B.base.lacc = L;
-                B.base.eps = (float)(b->d[0].weno_eps > 0.0 ? b->d[0].weno_eps : 1e-6);
                 B.base.clamps = b->d_clamps;
                 B.base.first = 1;
                 B.base.stage = rh::STAGE_WRITE_L;
@@ -931,7 +930,6 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
             B.base.us = (const double*)b->state;
             B.base.u0 = (const double*)b->state;
             B.base.lacc = L;
-            B.base.eps = b->d[0].weno_eps > 0.0 ? b->d[0].weno_eps : 1e-6;
             B.base.clamps = b->d_clamps;
             B.base.first = 1;
             B.base.stage = rh::STAGE_WRITE_L;
@@ -1215,3 +1213,4 @@ rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const vo
 }
 
 }  // extern "C"
+

@@ -42,8 +42,10 @@ struct BatchGrid {
     int blk0[3];     // first block of this grid in the launch of sweep class 0/1/2
     int seg[3];      // rolling segment length along y (1) and z (2)
     int nchunk[3];   // 256-lane chunks of the (x, w) plane for y (1) and z (2)
+    T eps;           // WENO epsilon of this grid
     double c0[3];
     double h[3];
+    double t0, e0, n0;   // analytic (HUBBLE) boundary parameters of this grid
 };
 
 template <class T>

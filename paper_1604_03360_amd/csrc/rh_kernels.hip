@@ -134,7 +134,11 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs<T>& A, int blk) {
         if (row < nrows && gx < nx + G) {
             T u[5], fp[5], fm[5];
             load_cell_x<T>(A, gx, row, u);
-            split_flux<T, 0>(u, fp, fm, clamped);
+            unsigned c = 0;
+            split_flux<T, 0>(u, fp, fm, c);
+            // floors are counted once per cell and evaluation of L: by the
+            // first sweep, for the cells it owns
+            if (A.first && lx >= G && lx < G + TX && gx < nx) clamped += c;
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 sp[(c * TY + ly) * PW + lx] = fp[c];
@@ -246,7 +250,9 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
         T u[5], fp[5], fm[5];
         fetch(k0 - R + j, u);
         if (j >= R && combine) ring_put(k0 - R + j, u);
-        split_flux<T, DIR>(u, fp, fm, clamped);
+        unsigned c = 0;
+        split_flux<T, DIR>(u, fp, fm, c);
+        if (A.first && j >= R && k0 - R + j < kend) clamped += c;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             wp[c][j] = fp[c];
@@ -282,7 +288,9 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
         };
         if constexpr (sizeof(T) == 4) load_epilogue();
         T fp[5], fm[5];
-        split_flux<T, DIR>(u, fp, fm, clamped);
+        unsigned c = 0;
+        split_flux<T, DIR>(u, fp, fm, c);
+        if (A.first && k + R < kend) clamped += c;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
 #pragma unroll
@@ -321,23 +329,9 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
 
 // Minimum resident 256-thread blocks per CU for the rolling sweeps (= waves per
 // SIMD); caps the register window so that enough waves hide load latency.
-#ifndef RH_ROLL_MINB_F32_W5
-#define RH_ROLL_MINB_F32_W5 3
-#endif
-#ifndef RH_ROLL_MINB_F32_W7
-#define RH_ROLL_MINB_F32_W7 3
-#endif
-#ifndef RH_ROLL_MINB_F64_W5
-#define RH_ROLL_MINB_F64_W5 2
-#endif
-#ifndef RH_ROLL_MINB_F64_W7
-#define RH_ROLL_MINB_F64_W7 1
-#endif
-
 template <class T, int ORDER>
 struct RollMinBlocks {
-    static constexpr int value = sizeof(T) == 4 ? (ORDER == 5 ? RH_ROLL_MINB_F32_W5 : RH_ROLL_MINB_F32_W7)
-                                                : (ORDER == 5 ? RH_ROLL_MINB_F64_W5 : RH_ROLL_MINB_F64_W7);
+    static constexpr int value = sizeof(T) == 4 ? 3 : (ORDER == 5 ? 2 : 1);
 };
 
 template <class T, int ORDER, int TX>
@@ -382,6 +376,10 @@ __device__ __forceinline__ SweepArgs<T> grid_args(const BatchArgs<T>& B, int g, 
     A.bc = G.bc[d];
     A.inv_h = G.inv_h[d];
     A.seg = G.seg[d];
+    A.eps = G.eps;
+    A.hb.t0 = G.t0;
+    A.hb.e0 = G.e0;
+    A.hb.n0 = G.n0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         A.hb.c0[a] = G.c0[a];
@@ -574,11 +572,6 @@ int choose_tile_x(int nx, int ghosts) {
 }
 
 int choose_segment(int n, int ncol_lanes) {
-    static const int forced = [] {
-        const char* e = getenv("RH_ROLL_SEGMENT");
-        return e ? atoi(e) : 0;
-    }();
-    if (forced > 0) return forced < n ? forced : n;
     // enough lanes to fill the chip (about 2^19), segments no shorter than 16
     // cells (each segment recomputes 2R + 1 halo cells; at 96^3 segments of 16
     // instead of 32 double the lanes and measured 1.5x faster, at 256^3 the
@@ -662,9 +655,11 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
     // part of L of row m into the ring when the row is owned (uniform per block)
     auto enter = [&](int m, const T u[5], T fp[5], T fm[5]) {
         double kap, Mxs, Mys, p;
-        recover_kp((double)u[0], (double)u[1], (double)u[2], (double)u[3], kap, Mxs, Mys, p, clamped);
+        unsigned c = 0;
+        recover_kp((double)u[0], (double)u[1], (double)u[2], (double)u[3], kap, Mxs, Mys, p, c);
         split_flux_vp<T, 1>(u, (T)(kap * Mys), (T)p, fp, fm);
         if (m < k0 || m >= kend) return;
+        clamped += c;   // owned rows only: once per cell and evaluation of L
         T fpx[5], fmx[5];
         split_flux_vp<T, 0>(u, (T)(kap * Mxs), (T)p, fpx, fmx);
 #pragma unroll

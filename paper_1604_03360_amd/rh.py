@@ -11,8 +11,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# RH_LIBRARY selects another build of the same library (tuning variants)
-LIB_PATH = os.environ.get("RH_LIBRARY") or os.path.join(HERE, "librh.so")
+LIB_PATH = os.path.join(HERE, "librh.so")
 
 RH_OK, RH_E_INVAL, RH_E_NOMEM, RH_E_HIP, RH_E_STATE, RH_E_NOTSUP, RH_E_PHYS = 0, -1, -2, -3, -4, -5, -6
 RH_PREC_FP64, RH_PREC_FP32 = 0, 1

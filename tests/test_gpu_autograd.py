@@ -77,3 +77,30 @@ def test_adjoint_gradient_against_finite_differences(n, n_steps):
         noise = 100 * np.finfo(float).eps * abs(loss64) / hstep * 1.5
         assert abs(g64[idx] - fd) <= 1e-6 * gmax + noise + 1e-6 * abs(fd), (idx, g64[idx], fd)
         assert abs(g32[idx] - fd) <= 1e-3 * gmax, (idx, g32[idx], fd)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_step_after_backward_continues_the_forward_run(precision):
+    """backward replays checkpointed segments on the plan's own buffers; afterwards
+    the plan holds the forward's final state and time again, so further steps
+    equal those of an uninterrupted run, bitwise."""
+    from paper_1604_03360_amd import autograd
+    rh = rh_module()
+    prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
+    spec = inputs.diff_event(n=32)
+    dt = spec["dt"]
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    e0 = torch.tensor(spec["prim"][0], dtype=torch.float64, device="cuda").requires_grad_(True)
+    uT = autograd.run(initial_state(e0).to(h.dtype), h, dt, 7, every=3)
+    anisotropy(uT).backward()
+    assert h.t == pytest.approx(spec["t0"] + 7 * dt, abs=1e-12)
+    assert torch.equal(h.state, uT.detach())
+    h.step(dt, 4)
+    after = h.state.clone()
+    h.close()
+    ref = rh.Hydro.from_spec(spec, precision=prec)
+    with torch.no_grad():
+        ref.state.copy_(initial_state(e0.detach()).to(ref.dtype))
+    ref.step(dt, 11)
+    assert torch.equal(after, ref.state)
+    ref.close()

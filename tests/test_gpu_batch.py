@@ -166,3 +166,23 @@ def test_full_ensemble_sampled_events():
         u0 = oracle.prim2con(sp["prim"])
         scale = np.abs(u0).reshape(5, -1).sum(1).max()     # momenta start at zero
         assert np.all(np.abs(np.array(tot1[g]) - np.array(tot0[g])) <= 2e-6 * scale), g
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_grids_keep_their_own_eps_and_boundary_parameters(precision):
+    """Each grid of a batch is advanced with its own WENO epsilon and its own
+    analytic-boundary parameters: every event equals its single-grid run bitwise."""
+    rh = rh_module()
+    prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
+    a = inputs.hotspots(0, size=24)
+    b = dict(inputs.hotspots(1, size=32))
+    b["eps"] = 1e-2
+    c = inputs.hubble(n=20, half_width=3.0)
+    d = dict(inputs.hubble(n=16, half_width=3.0, e0=2.0, n0=0.25))
+    d["eps"] = 1e-3
+    for specs in ([a, b], [c, d]):
+        dt = min(sp["dt"] for sp in specs)
+        got, _, _ = run_batch(rh, specs, prec, 3, dt)
+        for sp, u in zip(specs, got):
+            ref = run_single(rh, sp, prec, 3, dt)
+            assert np.array_equal(u, ref), (sp["name"], sp["eps"], sp["hub"])

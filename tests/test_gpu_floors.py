@@ -1,0 +1,205 @@
+"""The primitive-recovery floors on the GPU against the FP64 oracle.
+
+The recovery floors act where the conserved state has no physical primitive
+state: E below 1e-12 (the cell is treated as at rest with p = max(E, 0)/3) and
+|M| at or above the velocity cap (M is rescaled to |v| = 1 - 1e-12).  Neither
+is reached by the smooth workloads, so these tests plant such cells into smooth
+states -- tiny, zero and negative E, |M| > E, and both at once -- at random
+interior positions and on the faces of the grid, and compare element by element:
+
+  * L(u), one SSP-RK3 step, J(u)^T w and the adjoint of one step, on grids that
+    take every kernel variant (tiled x sweep, fused x-y sweep, whole-row and
+    tiled x adjoints, rolling y/z sweeps; periodic and outflow boundaries),
+    WENO5 and WENO7, FP64 and FP32;
+  * the floor counter after one evaluation of L against the number of floored
+    cells the oracle's own recovery reports for the same state.
+
+Bars: FP64 1e-12; FP32 5e-5 against the oracle run on the FP32-rounded inputs
+(normalised per field as in the other parity tests).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_03360_amd import inputs
+from gpu_helpers import L_errors, field_errors, rh_module
+
+FP64_TOL = 1e-12
+FP32_TOL = 5e-5
+
+CASES = {
+    # tiled x sweep and tiled x adjoint with its separate pack; rolling y and z
+    "periodic_tiled": lambda o: inputs.random_smooth((70, 37, 23), h=0.1, seed=91, order=o),
+    # outflow ghosts fold onto the planted edge cells
+    "outflow": lambda o: inputs.random_smooth((33, 20, 45), h=0.07, seed=92, order=o,
+                                              bc=(inputs.BC_OUTFLOW,) * 3),
+    # whole periodic rows: fused x-y sweep and whole-row x adjoint
+    "periodic_rows": lambda o: inputs.random_smooth((64, 24, 20), h=0.1, seed=93, order=o),
+}
+
+
+def planted_state(spec, seed):
+    """Conserved state of the spec with unphysical cells planted (returns u and
+    the planted flat cell indices)."""
+    u = oracle.prim2con(spec["prim"]).copy()
+    nx, ny, nz = spec["shape"]
+    rng = np.random.default_rng([seed, 5])
+    cells = [tuple(int(rng.integers(0, s)) for s in (nz, ny, nx)) for _ in range(14)]
+    # faces of the grid (ghost maps of outflow and periodic axes)
+    cells += [(0, ny // 2, nx // 3), (nz - 1, 1, nx - 1), (nz // 2, 0, 0), (2, ny - 1, nx // 2),
+              (nz // 3, ny // 3, 0), (nz - 2, ny - 2, nx - 1)]
+    Etyp = float(np.median(u[0]))
+    for k, (z, y, x) in enumerate(cells):
+        kind = k % 6
+        E = u[0, z, y, x]
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        if kind == 0:      # below the energy floor, at rest
+            u[0, z, y, x] = 3e-13
+            u[1:4, z, y, x] = 0.0
+        elif kind == 1:    # zero energy with some momentum
+            u[0, z, y, x] = 0.0
+            u[1:4, z, y, x] = 1e-3 * Etyp * d
+        elif kind == 2:    # negative energy
+            u[0, z, y, x] = -0.01 * Etyp
+        elif kind == 3:    # |M| = 2E: the velocity cap
+            u[1:4, z, y, x] = 2.0 * E * d
+        elif kind == 4:    # |M| just above E
+            u[1:4, z, y, x] = (1.0 + 1e-6) * E * d
+        else:              # below the energy floor with |M| >> E (the energy floor wins)
+            u[0, z, y, x] = 5e-13
+            u[1:4, z, y, x] = 10.0 * 5e-13 * d
+    flat = sorted({(z * ny + y) * nx + x for z, y, x in cells})
+    return u, flat
+
+
+def _inputs(spec, prec, rh, seed):
+    u, planted = planted_state(spec, seed)
+    w = np.random.default_rng([seed, 9]).normal(size=u.shape)
+    if prec == rh.RH_PREC_FP32:
+        # both sides start from the FP32-rounded numbers
+        u = u.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+    return u, w, planted
+
+
+def _hydro(rh, spec, prec, u):
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    h.set_conserved(u)
+    rh.rh_reset_counters(h.plan)
+    return h
+
+
+def vjp_errors(got, ref, w, h):
+    got = np.asarray(got, np.float64).reshape(5, -1)
+    ref = np.asarray(ref, np.float64).reshape(5, -1)
+    scale = max(np.abs(ref).max(), np.abs(w).max() / h)
+    return np.abs(got - ref).max(axis=1) / scale
+
+
+PRECS = ["fp64", "fp32"]
+
+
+def _prec(rh, name):
+    return (rh.RH_PREC_FP64, FP64_TOL) if name == "fp64" else (rh.RH_PREC_FP32, FP32_TOL)
+
+
+def test_planted_cells_take_every_floor_branch(orc):
+    """The planted state reaches all three branches of the oracle's recovery:
+    the energy floor, the velocity cap, and (elsewhere) the plain closed form."""
+    spec = CASES["periodic_tiled"](5)
+    u, planted = planted_state(spec, 1)
+    prim, clamps = orc.con2prim(u, return_clamps=True)
+    assert clamps == len(planted)
+    flat_u = u.reshape(5, -1)
+    E, M2 = flat_u[0, planted], (flat_u[1:4, planted] ** 2).sum(0)
+    assert np.any(E <= 0.0) and np.any((E > 0.0) & (E < 1e-12))
+    assert np.any((E >= 1e-12) & (M2 > E * E))
+    v2 = (prim.reshape(5, -1)[1:4, planted] ** 2).sum(0)
+    assert np.all(v2 < 1.0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_L_with_floors_matches_oracle(case, order, precision):
+    rh = rh_module()
+    prec, tol = _prec(rh, precision)
+    spec = CASES[case](order)
+    u, _, planted = _inputs(spec, prec, rh, 11)
+    h = _hydro(rh, spec, prec, u)
+    got = h.apply_L().double().cpu().numpy()
+    _, cnt = h.totals()
+    h.close()
+    g = oracle.grid_from_spec(spec)
+    ref = oracle.apply_L(g, u)
+    err = L_errors(got, ref, u, min(spec["h"]))
+    _, floored = oracle.con2prim(u, return_clamps=True)
+    print(case, order, precision, "L", err, "floors", cnt[0], floored, flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= tol), err
+    # each floored cell is counted once per evaluation of L
+    assert floored == len(planted)
+    assert cnt[0] == floored
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_step_with_floors_matches_oracle(case, order, precision):
+    rh = rh_module()
+    prec, tol = _prec(rh, precision)
+    spec = CASES[case](order)
+    u, _, planted = _inputs(spec, prec, rh, 12)
+    h = _hydro(rh, spec, prec, u)
+    h.step(spec["dt"], 1)
+    got = h.get()
+    _, cnt = h.totals()
+    h.close()
+    ref, _ = oracle.step(oracle.grid_from_spec(spec), u, spec["dt"], 1)
+    err = field_errors(got, ref)
+    print(case, order, precision, "step", err, "floors", cnt[0], flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= tol), err
+    assert cnt[0] >= len(planted)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_vjp_with_floors_matches_oracle(case, order, precision):
+    rh = rh_module()
+    prec, tol = _prec(rh, precision)
+    spec = CASES[case](order)
+    u, w, _ = _inputs(spec, prec, rh, 13)
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    got = h.vjp(u, w).double().cpu().numpy()
+    h.close()
+    ref = oracle.vjp_L(oracle.grid_from_spec(spec), u, w)
+    err = vjp_errors(got, ref, w, min(spec["h"]))
+    print(case, order, precision, "vjp", err, flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= tol), err
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("order", [5, 7])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_step_vjp_with_floors_matches_oracle(case, order, precision):
+    rh = rh_module()
+    prec, tol = _prec(rh, precision)
+    spec = CASES[case](order)
+    u, w, _ = _inputs(spec, prec, rh, 14)
+    dt = spec["dt"]
+    h = rh.Hydro.from_spec(spec, precision=prec)
+    got = h.step_vjp(u, w, dt).double().cpu().numpy()
+    h.close()
+    ref = oracle.vjp_step(oracle.grid_from_spec(spec), u, w, dt)
+    err = np.abs(got - ref).reshape(5, -1).max(axis=1) / np.abs(ref).max()
+    print(case, order, precision, "step_vjp", err, flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= tol), err

@@ -1,17 +1,17 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark
 times (the library's default tile and segment choice for the shape).
 
-* the 256^3 ellipsoidal blob (WENO5 and WENO7, FP64 and FP32): one SSP-RK3 step,
-  every cell of every field against the FP64 oracle's step;
+* the 256^3 ellipsoidal blob (WENO5 and WENO7, FP64 and FP32): three SSP-RK3
+  steps, every cell of every field against the FP64 oracle's steps;
 * the 128^3 Hubble-like flow on [-5, 5]^3 with analytic ghosts: ten steps, FP64
   and FP32, against the oracle, and the whole 100-step run (FP64 against the
   oracle, FP32 against FP64, the energy density against its closed form);
-* the 64-event hot-spot ensemble advanced as one batch: the smallest and the
-  largest events against the oracle run of the same event alone;
+* the 64-event hot-spot ensemble advanced as one batch for ten steps: the
+  smallest and the largest events against the oracle run of the same event alone;
 * the blob's full run length (200 steps) on a 64^3 variant.
 
 Bars as in the small-grid parity tests: 1e-12 (FP64) and 2e-5 (FP32) normalised
-L-infinity per field.
+L-infinity per field (1e-5 for FP32 on the smooth Hubble-like flow).
 """
 import numpy as np
 import pytest
@@ -32,22 +32,26 @@ def blob_specs():
 def blob_oracle(blob_specs):
     cache = {}
 
-    def get(order):
-        if order not in cache:
-            cache[order] = oracle_steps(blob_specs[order], 1)[0]
-        return cache[order]
+    def get(order, nsteps):
+        if (order, nsteps) not in cache:
+            print("oracle: blob 256^3 WENO%d, %d step(s)" % (order, nsteps), flush=True)
+            cache[(order, nsteps)] = oracle_steps(blob_specs[order], nsteps)[0]
+        return cache[(order, nsteps)]
     return get
+
+
+BLOB_STEPS = 3
 
 
 @pytest.mark.parametrize("order", [5, 7])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
-def test_blob_256_one_step(order, precision, tol, blob_specs, blob_oracle):
+def test_blob_256_three_steps(order, precision, tol, blob_specs, blob_oracle):
     rh = rh_module()
     prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
     spec = blob_specs[order]
     print("blob 256^3 WENO%d %s" % (order, precision), flush=True)
-    got, _, _, cnt = gpu_steps(spec, prec, 1)
-    err = field_errors(got, blob_oracle(order))
+    got, _, _, cnt = gpu_steps(spec, prec, BLOB_STEPS)
+    err = field_errors(got, blob_oracle(order, BLOB_STEPS))
     print(err, flush=True)
     assert np.all(np.isfinite(got))
     assert np.all(err <= tol), err
@@ -78,13 +82,14 @@ def test_ensemble_events_against_oracle():
     print("ensemble of %d events, checking %s" % (len(specs), picks), flush=True)
     b = rh.Batch(specs, precision=rh.RH_PREC_FP32)
     b.set_primitive([sp["prim"] for sp in specs])
-    b.step(dt, 1)
+    rh.rh_batch_set_graph(b.batch, True)   # as the benchmark runs it
+    b.step(dt, 10)
     got = b.get()
     _, cnt = b.totals()
     b.close()
     assert cnt[1] == 0
     for g in picks:
-        ref, _ = oracle_steps(specs[g], 1)
+        ref, _ = oracle_steps(specs[g], 10)
         err = field_errors(got[g], ref)
         print(g, sizes[g], err, flush=True)
         assert np.all(err <= 2e-5), (g, err)
@@ -132,7 +137,7 @@ def test_blob_64_full_length():
     err32 = field_errors(g32, g64)
     print("blob 64^3 x 200: fp64 vs oracle", err64, "fp32 vs fp64", err32, flush=True)
     assert np.all(err64 <= 1e-12), err64
-    assert np.all(err32 <= 1e-4), err32
+    assert np.all(err32 <= 2e-5), err32
     assert cnt == [0, 0] and cnt32[1] == 0
 
 
@@ -141,10 +146,11 @@ def test_blob_256_adjoint_against_oracle(blob_specs, blob_oracle):
     times (whole-row x kernel over 256-cell rows, y and z sweeps in 32-cell
     segments), at the blob's state after one step (the oracle's), against the
     oracle's adjoint, normalised by max(max|ref|, max|w|/h): FP64 to 1e-12; FP32
-    on the FP32-rounded inputs to four times the problem's own sensitivity to
-    FP32 rounding (the oracle's change when u moves by a random half FP32 ulp:
-    about 9e-5 at this state, where e spans 1e-3 to 20 and the WENO weight
-    derivatives amplify it), and never looser than needed below 5e-5.  Then the
+    on the FP32-rounded inputs to 5e-5 where the problem allows it, else to four
+    times the problem's own sensitivity to FP32 rounding (the oracle's change
+    when u moves by a random half FP32 ulp: about 9e-5 at this state, where e
+    spans 1e-3 to 20 and the WENO weight derivatives amplify it), capped at a
+    fixed 2e-4 (measured errors 2e-5 to 1e-4).  Then the
     adjoint of one FP32 step from stored stages (the timed call) equals the
     recomputing one bitwise and the FP64 one on the same rounded inputs to the
     same bar."""
@@ -152,7 +158,7 @@ def test_blob_256_adjoint_against_oracle(blob_specs, blob_oracle):
     rh = rh_module()
     spec = blob_specs[5]
     g = oracle.grid_from_spec(spec)
-    u = blob_oracle(5)
+    u = blob_oracle(5, 1)
     w = np.random.default_rng(256).normal(size=u.shape)
     t, dt, h = spec["t0"] + spec["dt"], spec["dt"], min(spec["h"])
 
@@ -176,12 +182,11 @@ def test_blob_256_adjoint_against_oracle(blob_specs, blob_oracle):
     up = u32 * (1.0 + 2.0 ** -24 * np.random.default_rng(257).uniform(-1.0, 1.0, size=u.shape))
     sens = errs(oracle.vjp_L(g, up, w32, t=t), ref32, w32).max()
     del up
-    bar = max(5e-5, 4.0 * sens)
+    bar = min(2e-4, max(5e-5, 4.0 * sens))
     h32 = rh.Hydro.from_spec(spec, precision=rh.RH_PREC_FP32)
     got = h32.vjp(u32, w32, t=t).double().cpu().numpy()
     err = errs(got, ref32, w32)
     print("fp32", err, "sensitivity to a half-ulp change of u %.3e, bar %.3e" % (sens, bar), flush=True)
-    assert sens < 1e-3, sens
     assert np.all(err <= bar), err
     del got, ref32
 
