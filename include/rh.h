@@ -70,7 +70,19 @@ typedef int rh_status;
 #define RH_KERNEL_SWEEP_XY 5  /* fused x and y sweep (WENO5, and WENO7 in FP32; periodic x of
                                  64..256 cells, a multiple of 64): one launch in place of the x
                                  and y sweeps */
-#define RH_KERNEL_CLASSES 6
+#define RH_KERNEL_STAGE 6     /* fused stage: x, y and z of L and the stage combine in one launch */
+#define RH_KERNEL_CLASSES 7
+
+/* Evaluation paths of L (rh_set_path, rh_batch_set_path).  RH_PATH_SWEEPS: one
+ * directional sweep per axis (x, y, z; the x and y sweeps fused into one launch
+ * where rh_kernel_times reports RH_KERNEL_SWEEP_XY) with an L accumulator in the
+ * workspace.  RH_PATH_STAGE: one launch per Runge-Kutta stage evaluating all three
+ * axes of L and the stage combine (no L accumulator); it needs more than one
+ * cell on every axis.  Both give bitwise the same results.  RH_PATH_AUTO (the
+ * default) takes RH_PATH_SWEEPS for single grids and RH_PATH_STAGE for batches. */
+#define RH_PATH_AUTO   0
+#define RH_PATH_SWEEPS 1
+#define RH_PATH_STAGE  2
 
 typedef struct rh_grid_desc {
     int nx, ny, nz;          /* cells per axis, each >= 1 */
@@ -170,6 +182,24 @@ rh_status rh_totals(rh_plan* plan, double out[5], long long counters[2]);
  * Errors: RH_E_INVAL (NULL plan). */
 rh_status rh_set_graph(rh_plan* plan, int enable);
 
+/* Select the evaluation path (RH_PATH_*) of every later call that evaluates L
+ * (rh_apply_L, rh_step, rh_step_store and the stage recomputation of
+ * rh_step_vjp).  Drops a captured step graph.
+ * Errors: RH_E_INVAL (unknown path), RH_E_NOTSUP (RH_PATH_STAGE on a grid with
+ * an axis of one cell). */
+rh_status rh_set_path(rh_plan* plan, int path);
+
+/* The path the plan's evaluations take now (RH_PATH_SWEEPS or RH_PATH_STAGE). */
+rh_status rh_get_path(const rh_plan* plan, int* path);
+
+/* Launch shape of the fused stage: tile_x (16, or 32 for WENO5) cells along x by 256/tile_x
+ * along y per block, and the z segment each block rolls along (seg_z >= 1;
+ * 0 selects a default for the grid, clamped to nz).  Drops a captured step
+ * graph.  rh_get_stage_tuning reports the shape in use (the segment resolved).
+ * Errors: RH_E_INVAL. */
+rh_status rh_set_stage_tuning(rh_plan* plan, int tile_x, int seg_z);
+rh_status rh_get_stage_tuning(const rh_plan* plan, int* tile_x, int* seg_z);
+
 /* Reset the floor counter reported by rh_totals to zero (asynchronous). */
 rh_status rh_reset_counters(rh_plan* plan);
 
@@ -232,7 +262,8 @@ rh_status rh_step_vjp_stored(rh_plan* plan, double t, double dt, const void* u_n
  * Event-by-event ensembles (batched grids).  The paper's motivation is
  * event-by-event simulation of many independent collisions (abstract and
  * Sec. 1 introduction); a batch advances many independent grids together with
- * one launch per directional sweep per Runge-Kutta stage covering every grid.
+ * one launch per Runge-Kutta stage covering every grid (RH_PATH_STAGE, the
+ * default), or one launch per directional sweep and stage (RH_PATH_SWEEPS).
  * ------------------------------------------------------------------------ */
 typedef struct rh_batch rh_batch;
 
@@ -262,10 +293,11 @@ rh_status rh_batch_bind(rh_batch* batch, void* state, void* workspace, void* str
 rh_status rh_batch_set_fields(rh_batch* batch, const double* src, int kind);
 rh_status rh_batch_get_fields(rh_batch* batch, double* dst, int kind);
 
-/* Advance every grid n_steps SSP-RK3 steps of size dt (Sec. 1).  Each stage is
- * three launches (x, y, z sweeps), each covering all grids; with graphs
- * enabled the nine launches of a step are captured once in a hipGraph and
- * replayed.  Errors as rh_step. */
+/* Advance every grid n_steps SSP-RK3 steps of size dt (Sec. 1).  On the
+ * default path each stage is one launch covering all grids (x, y and z of L
+ * and the stage combine); with RH_PATH_SWEEPS it is three (x, y, z sweeps).
+ * With graphs enabled the launches of one step are captured once in a
+ * hipGraph and replayed.  Errors as rh_step. */
 rh_status rh_batch_step(rh_batch* batch, double dt, int n_steps, double* t_inout);
 
 /* Per-grid FP64 totals out[n_grids][5] (E, Mx, My, Mz, N) and counters as
@@ -277,14 +309,25 @@ rh_status rh_batch_totals(rh_batch* batch, double* out, long long counters[2]);
  * depend on the stage time. */
 rh_status rh_batch_set_graph(rh_batch* batch, int enable);
 
-/* Launch shape of the batched sweeps: x tile width (64, 32 or 16 cells) and
- * the rolling segment lengths along y and z (>= 4 cells). */
+/* Evaluation path of the batch (RH_PATH_*; as rh_set_path).  Drops a captured
+ * step graph.  Errors: RH_E_INVAL. */
+rh_status rh_batch_set_path(rh_batch* batch, int path);
+rh_status rh_batch_get_path(const rh_batch* batch, int* path);
+
+/* Launch shape of the batched directional sweeps (RH_PATH_SWEEPS): x tile width
+ * (64, 32 or 16 cells) and the rolling segment lengths along y and z (>= 4). */
 rh_status rh_batch_set_tuning(rh_batch* batch, int tile_x, int seg_y, int seg_z);
 rh_status rh_batch_get_tuning(const rh_batch* batch, int* tile_x, int* seg_y, int* seg_z);
 
-/* Time the candidate launch shapes on the bound state (evaluations of L into
- * the workspace; the state is not modified) with HIP events, keep the fastest
- * and report it through rh_batch_get_tuning.  reps >= 1 timed launches per
+/* Launch shape of the batched fused stage (RH_PATH_STAGE): x-y tile width (16
+ * or 32 cells) and z segment (>= 1, clamped to each grid's nz). */
+rh_status rh_batch_set_stage_tuning(rh_batch* batch, int tile_x, int seg_z);
+rh_status rh_batch_get_stage_tuning(const rh_batch* batch, int* tile_x, int* seg_z);
+
+/* Time the candidate launch shapes of the batch's path on the bound state
+ * (evaluations of L into the workspace; the state is not modified) with HIP
+ * events, keep the fastest and report it through rh_batch_get_stage_tuning
+ * (fused stage) or rh_batch_get_tuning (sweeps).  reps >= 1 timed launches per
  * candidate.  Synchronises the stream. */
 rh_status rh_batch_autotune(rh_batch* batch, int reps);
 

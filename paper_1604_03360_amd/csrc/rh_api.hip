@@ -53,6 +53,10 @@ struct rh_plan {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
+    // evaluation path (RH_PATH_*) and the fused stage's launch shape
+    int path = RH_PATH_AUTO;
+    int stage_tx = 16;
+    int stage_seg = 0;           // 0: default segment for the grid
     // one captured step, replayed by rh_step when enabled
     bool graph_on = false;
     hipStream_t cap_stream = nullptr;
@@ -117,6 +121,41 @@ rh::SweepArgs<T> base_args(rh_plan* p) {
     return a;
 }
 
+bool any_hubble(const rh_plan* p) {
+    return p->d.bc[0] == RH_BC_HUBBLE || p->d.bc[1] == RH_BC_HUBBLE || p->d.bc[2] == RH_BC_HUBBLE;
+}
+
+// Grid entry of a fused-stage launch for description d at element offset off.
+template <class T>
+void fill_stage_grid(rh::StageGrid<T>& g, const rh_grid_desc& d, long long off, int tx, int seg) {
+    std::memset(&g, 0, sizeof(g));
+    g.off = off;
+    g.n[0] = d.nx;
+    g.n[1] = d.ny;
+    g.n[2] = d.nz;
+    const double h[3] = {d.dx, d.dy, d.dz};
+    const double c0[3] = {d.x0, d.y0, d.z0};
+    for (int a = 0; a < 3; ++a) {
+        g.bc[a] = d.bc[a];
+        g.inv_h[a] = (T)(1.0 / h[a]);
+        g.h[a] = h[a];
+        g.c0[a] = c0[a];
+    }
+    g.eps = (T)(d.weno_eps > 0.0 ? d.weno_eps : 1e-6);
+    g.t0 = d.hubble_t0;
+    g.e0 = d.hubble_e0;
+    g.n0 = d.hubble_n0;
+    rh::stage_shape<T>(g, tx, seg);
+}
+
+// Path of a single grid's evaluations: the fused stage where it is requested
+// and applies; RH_PATH_AUTO keeps the directional sweeps.
+bool use_stage(const rh_plan* p) {
+    const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
+    if (!rh::stage_fused_applies(n)) return false;
+    return p->path == RH_PATH_STAGE;
+}
+
 // One evaluation of L at time t on `us`; stage == 0 stores L in `lacc`,
 // otherwise the stage combine writes `uout` from `us`, `u0` and dt.
 template <class T>
@@ -142,6 +181,24 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
                                 "fill launch");
         return timed_launch(p, RH_KERNEL_OTHER, [&] { return rh::launch_combine<T>(a, p->stream); },
                             "combine launch");
+    }
+    if (use_stage(p)) {
+        rh::StageArgs<T> sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.us = us;
+        sa.u0 = u0;
+        sa.out = stage == rh::STAGE_WRITE_L ? lacc : uout;
+        sa.dt = (T)dt;
+        sa.stage = stage;
+        sa.t = t;
+        sa.clamps = p->d_clamps;
+        sa.ngrid = 0;
+        fill_stage_grid<T>(sa.one, p->d, 0, p->stage_tx,
+                           p->stage_seg > 0 ? p->stage_seg : rh::stage_default_segment(n, p->stage_tx));
+        const long long nb = rh::stage_blocks(sa.one);
+        return timed_launch(p, RH_KERNEL_STAGE, [&] {
+            return rh::launch_stage<T>(p->d.scheme, p->stage_tx, any_hubble(p), sa, nb, p->stream);
+        }, "stage launch");
     }
     int i0 = 0;
     if (na >= 2 && active[0] == 0 && active[1] == 1 && rh::sweep_xy_applies(p->d.scheme, sizeof(T) == 4, n, p->d.bc[0])) {
@@ -191,10 +248,6 @@ void drop_graph(rh_plan* p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->graph_exec = nullptr;
     p->graph = nullptr;
-}
-
-bool any_hubble(const rh_plan* p) {
-    return p->d.bc[0] == RH_BC_HUBBLE || p->d.bc[1] == RH_BC_HUBBLE || p->d.bc[2] == RH_BC_HUBBLE;
 }
 
 // n steps: eager launches, or replays of one captured step when graphs are on
@@ -402,6 +455,44 @@ rh_status rh_set_graph(rh_plan* p, int enable) {
     return RH_OK;
 }
 
+rh_status rh_set_path(rh_plan* p, int path) {
+    if (!p) return fail(RH_E_INVAL, "plan is NULL");
+    if (path != RH_PATH_AUTO && path != RH_PATH_SWEEPS && path != RH_PATH_STAGE)
+        return fail(RH_E_INVAL, "unknown path");
+    const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
+    if (path == RH_PATH_STAGE && !rh::stage_fused_applies(n))
+        return fail(RH_E_NOTSUP, "the fused stage needs more than one cell on every axis");
+    p->path = path;
+    drop_graph(p);
+    return RH_OK;
+}
+
+rh_status rh_get_path(const rh_plan* p, int* path) {
+    if (!p || !path) return fail(RH_E_INVAL, "NULL argument");
+    *path = use_stage(p) ? RH_PATH_STAGE : RH_PATH_SWEEPS;
+    return RH_OK;
+}
+
+rh_status rh_set_stage_tuning(rh_plan* p, int tile_x, int seg_z) {
+    if (!p) return fail(RH_E_INVAL, "plan is NULL");
+    if (tile_x != 16 && tile_x != 32) return fail(RH_E_INVAL, "tile_x must be 16 or 32");
+    if (tile_x == 32 && p->d.scheme == 7) return fail(RH_E_NOTSUP, "WENO7 stage tiles are 16 cells wide");
+    if (seg_z < 0) return fail(RH_E_INVAL, "seg_z must be >= 0 (0 = default)");
+    p->stage_tx = tile_x;
+    p->stage_seg = seg_z;
+    drop_graph(p);
+    return RH_OK;
+}
+
+rh_status rh_get_stage_tuning(const rh_plan* p, int* tile_x, int* seg_z) {
+    if (!p) return fail(RH_E_INVAL, "plan is NULL");
+    const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
+    if (tile_x) *tile_x = p->stage_tx;
+    if (seg_z) *seg_z = p->stage_seg > 0 ? (p->stage_seg < n[2] ? p->stage_seg : n[2])
+                                         : rh::stage_default_segment(n, p->stage_tx);
+    return RH_OK;
+}
+
 rh_status rh_totals(rh_plan* p, double out[5], long long counters[2]) {
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
@@ -479,10 +570,14 @@ struct rh_batch {
     int precision = RH_PREC_FP64;
     size_t elem = 8;
     bool any_hubble = false;
-    // launch shape
-    int tile_x = 32, seg[3] = {0, 32, 32};
+    // evaluation path and launch shapes
+    int path = RH_PATH_AUTO;
+    int tile_x = 32, seg[3] = {0, 32, 32};   // directional sweeps
     int nblocks[3] = {0, 0, 0};
     void* d_grids = nullptr;         // BatchGrid<T>[ngrid]
+    int stage_tx = 16, stage_seg = 32;       // fused stage
+    long long stage_nblocks = 0;
+    void* d_stage = nullptr;         // StageGrid<T>[ngrid]
     // binding
     void* state = nullptr;
     void* ws = nullptr;
@@ -555,6 +650,22 @@ rh_status upload_batch_table(rh_batch* b) {
     hipError_t e = hipMemcpy(b->d_grids, g.data(), g.size() * sizeof(rh::BatchGrid<T>),
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    // fused-stage table: grids in order, each a contiguous range of logical blocks
+    std::vector<rh::StageGrid<T>> sg(b->ngrid);
+    long long sacc = 0;
+    for (int i = 0; i < b->ngrid; ++i) {
+        fill_stage_grid<T>(sg[i], b->d[i], b->off[i], b->stage_tx, b->stage_seg);
+        sg[i].blk0 = (int)sacc;
+        sacc += rh::stage_blocks(sg[i]);
+        if (sacc > 0x7fffffffLL) return fail(RH_E_NOTSUP, "batch too large for one fused-stage launch");
+    }
+    b->stage_nblocks = sacc;
+    if (!b->d_stage) {
+        e = hipMalloc(&b->d_stage, sg.size() * sizeof(rh::StageGrid<T>));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(b->d_stage, sg.data(), sg.size() * sizeof(rh::StageGrid<T>), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     drop_graph(b);
     return RH_OK;
 }
@@ -593,6 +704,23 @@ rh_status batch_timed(rh_batch* b, hipStream_t s, int cls, F&& launch, const cha
 template <class T>
 rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T* lacc, T* uout,
                          double t, double dt, int stage) {
+    if (b->path != RH_PATH_SWEEPS) {
+        // one launch: L along x, y and z of every grid and the stage combine
+        rh::StageArgs<T> sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.us = us;
+        sa.u0 = u0;
+        sa.out = stage == rh::STAGE_WRITE_L ? lacc : uout;
+        sa.dt = (T)dt;
+        sa.stage = stage;
+        sa.t = t;
+        sa.clamps = b->d_clamps;
+        sa.grids = (const rh::StageGrid<T>*)b->d_stage;
+        sa.ngrid = b->ngrid;
+        return batch_timed(b, s, RH_KERNEL_STAGE, [&] {
+            return rh::launch_stage<T>(b->scheme, b->stage_tx, b->any_hubble, sa, b->stage_nblocks, s);
+        }, "batched stage launch");
+    }
     rh::BatchArgs<T> B;
     std::memset(&B, 0, sizeof(B));
     B.grids = (const rh::BatchGrid<T>*)b->d_grids;
@@ -754,6 +882,7 @@ void rh_batch_destroy(rh_batch* b) {
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->d_grids) (void)hipFree(b->d_grids);
+    if (b->d_stage) (void)hipFree(b->d_stage);
     if (b->d_clamps) (void)hipFree(b->d_clamps);
     if (b->d_partials) (void)hipFree(b->d_partials);
     if (b->d_totals) (void)hipFree(b->d_totals);
@@ -882,6 +1011,38 @@ rh_status rh_batch_set_tuning(rh_batch* b, int tile_x, int seg_y, int seg_z) {
     return upload_table(b);
 }
 
+rh_status rh_batch_set_path(rh_batch* b, int path) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (path != RH_PATH_AUTO && path != RH_PATH_SWEEPS && path != RH_PATH_STAGE)
+        return fail(RH_E_INVAL, "unknown path");
+    b->path = path;
+    drop_graph(b);
+    return RH_OK;
+}
+
+rh_status rh_batch_get_path(const rh_batch* b, int* path) {
+    if (!b || !path) return fail(RH_E_INVAL, "NULL argument");
+    *path = b->path == RH_PATH_SWEEPS ? RH_PATH_SWEEPS : RH_PATH_STAGE;
+    return RH_OK;
+}
+
+rh_status rh_batch_set_stage_tuning(rh_batch* b, int tile_x, int seg_z) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (tile_x != 16 && tile_x != 32) return fail(RH_E_INVAL, "tile_x must be 16 or 32");
+    if (tile_x == 32 && b->scheme == 7) return fail(RH_E_NOTSUP, "WENO7 stage tiles are 16 cells wide");
+    if (seg_z < 1) return fail(RH_E_INVAL, "seg_z must be >= 1");
+    b->stage_tx = tile_x;
+    b->stage_seg = seg_z;
+    return upload_table(b);
+}
+
+rh_status rh_batch_get_stage_tuning(const rh_batch* b, int* tile_x, int* seg_z) {
+    if (!b) return fail(RH_E_INVAL, "batch is NULL");
+    if (tile_x) *tile_x = b->stage_tx;
+    if (seg_z) *seg_z = b->stage_seg;
+    return RH_OK;
+}
+
 rh_status rh_batch_get_tuning(const rh_batch* b, int* tile_x, int* seg_y, int* seg_z) {
     if (!b) return fail(RH_E_INVAL, "batch is NULL");
     if (tile_x) *tile_x = b->tile_x;
@@ -946,6 +1107,74 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
         if ((e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
         return RH_OK;
     };
+    if (b->path != RH_PATH_SWEEPS) {
+        // fused stage: x-y tile width and z segment, timed on evaluations of L
+        // into the workspace's last state
+        auto time_stage = [&](float* ms) -> rh_status {
+            auto one = [&]() -> rh_status {
+                hipError_t er;
+                if (b->precision == RH_PREC_FP32) {
+                    rh::StageArgs<float> sa;
+                    std::memset(&sa, 0, sizeof(sa));
+                    sa.us = (const float*)b->state;
+                    sa.u0 = (const float*)b->state;
+                    sa.out = (float*)b->ws + 2 * S;
+                    sa.stage = rh::STAGE_WRITE_L;
+                    sa.clamps = b->d_clamps;
+                    sa.grids = (const rh::StageGrid<float>*)b->d_stage;
+                    sa.ngrid = b->ngrid;
+                    er = rh::launch_stage<float>(b->scheme, b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
+                } else {
+                    rh::StageArgs<double> sa;
+                    std::memset(&sa, 0, sizeof(sa));
+                    sa.us = (const double*)b->state;
+                    sa.u0 = (const double*)b->state;
+                    sa.out = (double*)b->ws + 2 * S;
+                    sa.stage = rh::STAGE_WRITE_L;
+                    sa.clamps = b->d_clamps;
+                    sa.grids = (const rh::StageGrid<double>*)b->d_stage;
+                    sa.ngrid = b->ngrid;
+                    er = rh::launch_stage<double>(b->scheme, b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
+                }
+                return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
+            };
+            rh_status s2 = one();   // warm-up
+            if (s2 != RH_OK) return s2;
+            if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            for (int r = 0; r < reps; ++r)
+                if ((s2 = one()) != RH_OK) return s2;
+            if ((e = hipEventRecord(e1, b->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            if ((e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            return RH_OK;
+        };
+        int btx = b->stage_tx, bseg = b->stage_seg;
+        float bms = 1e30f;
+        rh_status rs = RH_OK;
+        for (int tx : {16, 32}) {
+            if (tx == 32 && b->scheme == 7) continue;
+            for (int sg : {16, 24, 32, 48, 64}) {
+                b->stage_tx = tx;
+                b->stage_seg = sg;
+                if ((rs = upload_table(b)) != RH_OK) break;
+                float ms;
+                if ((rs = time_stage(&ms)) != RH_OK) break;
+                if (ms < bms) {
+                    bms = ms;
+                    btx = tx;
+                    bseg = sg;
+                }
+            }
+            if (rs != RH_OK) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->timing = saved_timing;
+        b->stage_tx = btx;
+        b->stage_seg = bseg;
+        rh_status up = upload_table(b);
+        return rs != RH_OK ? rs : up;
+    }
     int best_tx = b->tile_x, best_seg[3] = {0, b->seg[1], b->seg[2]};
     float best_ms = 1e30f;
     rh_status rs = RH_OK;

@@ -135,6 +135,42 @@ __device__ __forceinline__ void recover_kp(double E, double Mx, double My, doubl
     p = (E2 - M2) * a * r;
 }
 
+// The recovery for all three axes (v_d = kap * Ms_d), with the arithmetic of
+// recover_vp, so each v_d is bitwise the value recover_vp<d> returns.
+__device__ __forceinline__ void recover_kp3(double E, double Mx, double My, double Mz, double& kap,
+                                            double& Mxs, double& Mys, double& Mzs, double& p,
+                                            unsigned& clamped) {
+    if (E < kEFloor) {
+        kap = 0.0;
+        Mxs = 0.0;
+        Mys = 0.0;
+        Mzs = 0.0;
+        p = (E > 0.0 ? E : 0.0) / 3.0;
+        ++clamped;
+        return;
+    }
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    const double E2 = E * E;
+    const double cap = (1.0 - kVDelta) * E * E;
+    Mxs = Mx;
+    Mys = My;
+    Mzs = Mz;
+    if (M2 > cap) {
+        const double sc = sqrt(cap / M2);
+        Mxs *= sc;
+        Mys *= sc;
+        Mzs *= sc;
+        M2 = cap;
+        ++clamped;
+    }
+    const double D = sqrt_pos(4.0 * E2 - 3.0 * M2);
+    const double a = 2.0 * E + D;
+    const double b = E + D;
+    const double r = fast_rcp(a * b);
+    kap = 3.0 * b * r;
+    p = (E2 - M2) * a * r;
+}
+
 // Split fluxes f+- = (F_d(u) +- u) / 2 of one cell along axis DIR, given the
 // velocity along DIR and the pressure, returned doubled (F_d +- u).
 //

@@ -135,6 +135,56 @@ bool sweep_xy_applies(int order, bool fp32, const int n[3], int bc_x);
 template <class T>
 hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Fused stage: one launch evaluates L along x, y and z and applies the stage
+// combine (or stores L).  Work items are (grid, x-y tile, z segment).
+// ---------------------------------------------------------------------------
+template <class T>
+struct StageGrid {
+    long long off;          // element offset of this grid in every buffer
+    int n[3];
+    int bc[3];
+    T inv_h[3];
+    T eps;
+    int ntx, nty;           // tiles along x and y
+    int seg, nseg;          // z segment length and number of segments
+    int blk0;               // first (logical) block of this grid
+    double c0[3], h[3];     // cell-0 centre and widths (analytic boundaries)
+    double t0, e0, n0;      // analytic boundary parameters
+};
+
+template <class T>
+struct StageArgs {
+    const T* us;            // stage input
+    const T* u0;            // u^n (stages 2 and 3 read it pointwise)
+    T* out;                 // new state (stage > 0; may alias u0) or L (STAGE_WRITE_L)
+    T dt;
+    int stage;              // STAGE_*
+    double t;               // stage time (analytic boundaries)
+    unsigned* clamps;       // floor counter
+    const StageGrid<T>* grids;   // device table (ngrid > 0), sorted by blk0
+    int ngrid;              // 0: single grid in `one`
+    StageGrid<T> one;
+};
+
+// Tile width along x of the fused stage (16 or 32; 256 / tx rows along y).
+constexpr int kStageTiles[2] = {16, 32};
+// Fill ntx, nty, nseg (and seg, clamped to nz) of g for tile width tx and z segment seg.
+template <class T>
+void stage_shape(StageGrid<T>& g, int tx, int seg);
+template <class T>
+long long stage_blocks(const StageGrid<T>& g) {
+    return (long long)g.ntx * g.nty * g.nseg;
+}
+// True where the fused stage applies (every axis longer than one cell).
+bool stage_fused_applies(const int n[3]);
+// Launch the fused stage over nblocks blocks (tile width tx in {16, 32}); hub
+// selects the instantiation with analytic (HUBBLE) ghost cells.
+template <class T>
+hipError_t launch_stage(int order, int tx, bool hub, const StageArgs<T>& a, long long nblocks, hipStream_t s);
+// Default z segment of the fused stage for a grid of n cells (tiles of tx).
+int stage_default_segment(const int n[3], int tx);
+
 // Load / store through a uniform base pointer and a 32-bit byte offset (the
 // plan limits one field to < 4 GiB), so that address arithmetic stays 32-bit
 // per lane and the base lives in scalar registers.

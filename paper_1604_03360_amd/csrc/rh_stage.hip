@@ -1,0 +1,441 @@
+// rh_stage.hip -- one launch per SSP-RK3 stage for gfx950.
+//
+// stage_fused evaluates the whole operator L(u) of Eq. (2) (Sikorski et al.,
+// arXiv:1604.03360) -- the x, y and z flux differences -- and applies the
+// Runge-Kutta stage combine (Sec. 1) in a single launch, with no L accumulator
+// in memory.  A work item is (grid, x-y tile of TX x TY = 256 cells, z segment):
+// the block rolls along its z segment one plane at a time.  Each lane owns one
+// (x, y) column of the tile and keeps a register window of 2R doubled split
+// fluxes along z (as the rolling sweeps do); for every owned plane the block
+// stages the tile's doubled x and y split fluxes in LDS, with R halo cells on
+// each side along x and along y (no corners are needed), reconstructs every x
+// and y face of the tile once and keeps the x + y part of L for R planes until
+// the z face above the cell is known.  Every cell of the tile is loaded and
+// recovered (FP64) once per plane; the halo cells of the tile are recovered
+// again by the tiles that own them.
+//
+// The arithmetic of every face, flux difference and combine is that of the
+// split sweeps, summed in the same order (x, then y, then z), so the result is
+// bitwise that of the x, y and z sweeps run one after another.
+//
+// Ensembles use the same kernel: each block finds its grid in a table sorted
+// by first block, so one launch covers every grid of the batch.
+#include "rh_internal.hpp"
+#include "../../include/rh.h"
+
+namespace rh {
+
+namespace {
+
+// The chip hands consecutive blocks of a launch to its eight XCDs in turn
+// (block b to XCD b mod 8).  Renumbering gives every XCD a contiguous range of
+// logical blocks, so tiles that share halo cells meet in the same L2.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+__device__ __forceinline__ int ghost_index(int m, int nd, int bc) {
+    if (bc == RH_BC_PERIODIC) {
+        m %= nd;
+        return m < 0 ? m + nd : m;
+    }
+    return m < 0 ? 0 : nd - 1;   // outflow: zero-gradient copy of the edge cell
+}
+
+// State of cell (x, y, z) of grid G, of which at most one coordinate lies
+// outside the grid; ghost cells follow the boundary condition of that axis
+// (analytic ones are evaluated at the stage time t).  The analytic branch is
+// compiled only where HUB is set: inlined into the rolling loop its FP64
+// temporaries cost about 30 registers per lane even when never taken.
+template <class T, bool HUB>
+__device__ __forceinline__ void stage_load(const StageGrid<T>& G, const T* us, long long F, double t,
+                                           int x, int y, int z, T u[5]) {
+    bool analytic = false;
+    if (x < 0 || x >= G.n[0]) {
+        if (HUB && G.bc[0] == RH_BC_HUBBLE) analytic = true;
+        else x = ghost_index(x, G.n[0], G.bc[0]);
+    }
+    if (y < 0 || y >= G.n[1]) {
+        if (HUB && G.bc[1] == RH_BC_HUBBLE) analytic = true;
+        else y = ghost_index(y, G.n[1], G.bc[1]);
+    }
+    if (z < 0 || z >= G.n[2]) {
+        if (HUB && G.bc[2] == RH_BC_HUBBLE) analytic = true;
+        else z = ghost_index(z, G.n[2], G.bc[2]);
+    }
+    if (HUB && analytic) {
+        HubbleBC hb;
+        hb.t = t;
+        hb.t0 = G.t0;
+        hb.e0 = G.e0;
+        hb.n0 = G.n0;
+        double uh[5];
+        hubble_conserved(hb, G.c0[0] + x * G.h[0], G.c0[1] + y * G.h[1], G.c0[2] + z * G.h[2], uh);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f] = (T)uh[f];
+        return;
+    }
+    const uint32_t off = (uint32_t)sizeof(T) * ((uint32_t)x + (uint32_t)G.n[0] * ((uint32_t)y + (uint32_t)G.n[1] * (uint32_t)z));
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = ld_off(us + f * F, off);
+}
+
+// One reconstruction from a window of 2R doubled split fluxes of cells
+// i - R + 1 .. i + R (interface i + 1/2): plus = left-biased on f+, minus =
+// mirrored on f-.  eps2 is the epsilon of the doubled data (4 eps); WENO5
+// carries its smoothness indicators as 4 beta and takes 4 eps2.
+template <class T, int ORDER>
+__device__ __forceinline__ T stage_recon_plus(const T* w, T eps2) {
+    if constexpr (ORDER == 5) return weno5<T>(w[0], w[1], w[2], w[3], w[4], (T)4 * eps2);
+    else return weno7<T>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], eps2);
+}
+template <class T, int ORDER>
+__device__ __forceinline__ T stage_recon_minus(const T* w, T eps2) {
+    if constexpr (ORDER == 5) return weno5<T>(w[5], w[4], w[3], w[2], w[1], (T)4 * eps2);
+    else return weno7<T>(w[7], w[6], w[5], w[4], w[3], w[2], w[1], eps2);
+}
+
+}  // namespace
+
+// Minimum resident blocks per CU (= waves per SIMD) for the register budget;
+// FP64 blocks other than WENO5 16 x 16 need more than half of the 160 KB LDS.
+template <class T, int ORDER, int TX>
+struct StageMinBlocks {
+    static constexpr int value = sizeof(T) == 4 ? 3 : (ORDER == 5 && TX == 16 ? 2 : 1);
+};
+
+template <class T, int ORDER, int TX, bool HUB>
+__global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) stage_fused(StageArgs<T> A) {
+    constexpr int R = (ORDER + 1) / 2, W = 2 * R, TY = 256 / TX;
+    static_assert(W * (TX + TY) <= 256, "one halo cell per lane and plane");
+    static_assert(5 * (TX + TY) <= 256, "one edge face (all components) per lane");
+    constexpr int SX = TX + 2 * R;            // staged x row: R ghosts, TX cells, R ghosts
+    constexpr int SY = TY + 2 * R;
+    __shared__ T sx[2][5][TY][SX];            // doubled x split fluxes (plus, minus)
+    __shared__ T sy[2][5][SY][TX];            // doubled y split fluxes
+    __shared__ T fx[5][TY][TX + 1];           // x face fluxes: column 0 = left face of the tile, 1 + i = right face of cell i
+    __shared__ T fy[5][TY + 1][TX];           // y face fluxes: row 0 = lower face of the tile, 1 + j = upper face of row j
+
+    const int b = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+    int g = 0;
+    if (A.ngrid > 0) {
+        int lo = 0, hi = A.ngrid - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.grids[mid].blk0 <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        g = lo;
+    }
+    const StageGrid<T> G = A.ngrid > 0 ? A.grids[g] : A.one;
+    const int lb = b - G.blk0;
+    const int tpp = G.ntx * G.nty;
+    const int zs = lb / tpp, rem = lb - zs * tpp;
+    const int tyi = rem / G.ntx, txi = rem - tyi * G.ntx;
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int xa = min(TX, nx - x0), ya = min(TY, ny - y0);
+    const int k0 = zs * G.seg, kend = min(k0 + G.seg, nz);
+    const long long F = (long long)nx * ny * nz;
+    const T* us = A.us + G.off;
+    const T* u0 = A.u0 + G.off;
+    T* out = A.out + G.off;
+    const double t = A.t;
+
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const bool act = lx < xa && ly < ya;
+    // lanes outside a ragged tile follow the loop on a valid cell and store nothing
+    const int cx = x0 + min(lx, xa - 1), cy = y0 + min(ly, ya - 1);
+    const uint32_t sb = (uint32_t)sizeof(T) * (uint32_t)nx * (uint32_t)ny;   // z plane, bytes
+    const uint32_t cb = (uint32_t)sizeof(T) * ((uint32_t)cx + (uint32_t)nx * (uint32_t)cy);
+
+    // halo job of this lane: one x-halo cell (row r, staged column p; cell x0 - R + p)
+    // or one y-halo cell (column c, staged row q; cell y0 - R + q), the same every plane
+    const int nxh = W * ya, nyh = W * xa;
+    int hkind = 0, hr = 0, hc = 0, hxc = 0, hyc = 0;
+    if (tid < nxh) {
+        const int j = tid % W;
+        hkind = 1;
+        hr = tid / W;
+        hc = j < R ? j : xa + j;
+        hxc = x0 - R + hc;
+        hyc = y0 + hr;
+    } else if (tid < nxh + nyh) {
+        const int s = tid - nxh, j = s % W;
+        hkind = 2;
+        hc = s / W;
+        hr = j < R ? j : ya + j;
+        hxc = x0 + hc;
+        hyc = y0 - R + hr;
+    }
+
+    auto fetch_own = [&](int m, T u[5]) {
+        if (m >= 0 && m < nz) {
+            const uint32_t off = cb + (uint32_t)m * sb;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) u[f] = ld_off(us + f * F, off);
+        } else {
+            stage_load<T, HUB>(G, us, F, t, cx, cy, m, u);
+        }
+    };
+    auto fetch_halo = [&](int m, T u[5]) {
+        if (hkind) stage_load<T, HUB>(G, us, F, t, hxc, hyc, m, u);
+    };
+
+    const T eps2 = (T)4 * G.eps;   // epsilon of the doubled split fluxes
+    const T hxinv = (T)0.5 * G.inv_h[0], hyinv = (T)0.5 * G.inv_h[1], hzinv = (T)0.5 * G.inv_h[2];
+    unsigned clamped = 0;
+
+    T zp[5][W], zm[5][W];     // z window: doubled split fluxes of cells k - R .. k + R - 1
+    T ring[R][5];             // x + y part of L of the last R owned planes, oldest first
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) zp[c][j] = zm[c][j] = (T)0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) ring[j][c] = (T)0;
+    }
+
+    // Enter plane m: recover the own cell, shift its z split fluxes into the
+    // window and, for an owned plane, stage the x / y split fluxes of the own
+    // and halo cells.
+    auto enter = [&](int m, const T u[5], const T hu[5], bool owned) {
+        double kap, Mxs, Mys, Mzs, p;
+        unsigned c0 = 0;
+        recover_kp3((double)u[0], (double)u[1], (double)u[2], (double)u[3], kap, Mxs, Mys, Mzs, p, c0);
+        const T P = (T)p;
+        T fp[5], fm[5];
+        split_flux_vp<T, 2>(u, (T)(kap * Mzs), P, fp, fm);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+#pragma unroll
+            for (int j = 0; j < W - 1; ++j) {
+                zp[c][j] = zp[c][j + 1];
+                zm[c][j] = zm[c][j + 1];
+            }
+            zp[c][W - 1] = fp[c];
+            zm[c][W - 1] = fm[c];
+        }
+        if (!owned) return;
+        if (act) {
+            clamped += c0;   // floors counted once per owned cell and evaluation of L
+            split_flux_vp<T, 0>(u, (T)(kap * Mxs), P, fp, fm);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                sx[0][c][ly][R + lx] = fp[c];
+                sx[1][c][ly][R + lx] = fm[c];
+            }
+            split_flux_vp<T, 1>(u, (T)(kap * Mys), P, fp, fm);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                sy[0][c][R + ly][lx] = fp[c];
+                sy[1][c][R + ly][lx] = fm[c];
+            }
+        }
+        if (hkind) {
+            double hk, hMx, hMy, hp;
+            unsigned hcl = 0;
+            recover_kp((double)hu[0], (double)hu[1], (double)hu[2], (double)hu[3], hk, hMx, hMy, hp, hcl);
+            if (hkind == 1) {
+                split_flux_vp<T, 0>(hu, (T)(hk * hMx), (T)hp, fp, fm);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    sx[0][c][hr][hc] = fp[c];
+                    sx[1][c][hr][hc] = fm[c];
+                }
+            } else {
+                split_flux_vp<T, 1>(hu, (T)(hk * hMy), (T)hp, fp, fm);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    sy[0][c][hr][hc] = fp[c];
+                    sy[1][c][hr][hc] = fm[c];
+                }
+            }
+        }
+    };
+
+    // x + y part of L of the staged (owned) plane, pushed into the ring
+    auto plane_xy = [&]() {
+        __syncthreads();
+        if (act) {
+            // one component at a time: unrolled, the LDS reads of all five
+            // windows would be hoisted and raise the register peak
+#pragma unroll 1
+            for (int c = 0; c < 5; ++c) {
+                // window of face x + 1/2: staged columns lx + 1 .. lx + 2R
+                fx[c][ly][lx + 1] = stage_recon_plus<T, ORDER>(&sx[0][c][ly][lx + 1], eps2) +
+                                    stage_recon_minus<T, ORDER>(&sx[1][c][ly][lx + 1], eps2);
+                T wp[W], wm[W];
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    wp[j] = sy[0][c][ly + 1 + j][lx];
+                    wm[j] = sy[1][c][ly + 1 + j][lx];
+                }
+                fy[c][ly + 1][lx] = stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
+            }
+        }
+        // faces on the lower edges of the tile, one (line, component) per lane:
+        // 5 ya x jobs (window at staged column 0), then 5 xa y jobs (staged row 0)
+        if (tid < 5 * ya) {
+            const int r = tid / 5, c = tid - 5 * r;
+            fx[c][r][0] = stage_recon_plus<T, ORDER>(&sx[0][c][r][0], eps2) +
+                          stage_recon_minus<T, ORDER>(&sx[1][c][r][0], eps2);
+        } else if (tid < 5 * (ya + xa)) {
+            const int s = tid - 5 * ya, col = s / 5, c = s - 5 * col;
+            T wp[W], wm[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                wp[j] = sy[0][c][j][col];
+                wm[j] = sy[1][c][j][col];
+            }
+            fy[c][0][col] = stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R - 1; ++j)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) ring[j][c] = ring[j + 1][c];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T Lx = (fx[c][ly][lx] - fx[c][ly][lx + 1]) * hxinv;
+            const T Ly = (fy[c][ly][lx] - fy[c][ly + 1][lx]) * hyinv;
+            ring[R - 1][c] = Lx + Ly;
+        }
+    };
+    auto push_none = [&]() {
+#pragma unroll
+        for (int j = 0; j < R - 1; ++j)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) ring[j][c] = ring[j + 1][c];
+    };
+
+    // fill: planes k0 - R .. k0 + R - 1 (the z window of face k0 - 1/2)
+    T nu[5], nh[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+    fetch_own(k0 - R, nu);
+    for (int m = k0 - R; m < k0 + R; ++m) {
+        T u[5], hu[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            u[f] = nu[f];
+            hu[f] = nh[f];
+        }
+        const bool owned = m >= k0 && m < kend;
+        fetch_own(m + 1, nu);
+        if (m + 1 >= k0 && m + 1 < kend) fetch_halo(m + 1, nh);
+        enter(m, u, hu, owned);
+        if (owned) plane_xy();
+        else if (m >= k0) push_none();
+    }
+    T Fl[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        Fl[c] = stage_recon_plus<T, ORDER>(zp[c], eps2) + stage_recon_minus<T, ORDER>(zm[c], eps2);
+
+    // main loop: plane m = k + R enters, cell k is finished
+    for (int k = k0; k < kend; ++k) {
+        const int m = k + R;
+        T u[5], hu[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            u[f] = nu[f];
+            hu[f] = nh[f];
+        }
+        const bool owned = m < kend;
+        if (k + 1 < kend) fetch_own(m + 1, nu);
+        if (m + 1 < kend) fetch_halo(m + 1, nh);
+        const uint32_t off = cb + (uint32_t)k * sb;
+        enter(m, u, hu, owned);
+        T Lk[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T Fr = stage_recon_plus<T, ORDER>(zp[c], eps2) + stage_recon_minus<T, ORDER>(zm[c], eps2);
+            const T Lz = (Fl[c] - Fr) * hzinv;
+            Fl[c] = Fr;
+            Lk[c] = ring[0][c] + Lz;
+        }
+        // the stage input and u^n of cell k, loaded after the reconstructions
+        // to keep them out of the register peak
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T L = Lk[c];
+            const T usk = A.stage != STAGE_WRITE_L ? ld_off(us + c * F, off) : (T)0;
+            const T u0k = A.stage >= STAGE_2 ? ld_off(u0 + c * F, off) : (T)0;
+            T v;
+            if (A.stage == STAGE_WRITE_L) {
+                v = L;
+            } else {
+                v = usk + A.dt * L;
+                if (A.stage == STAGE_2) v = (T)0.75 * u0k + (T)0.25 * v;
+                else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * u0k + (T)(2.0 / 3.0) * v;
+            }
+            if (act) st_off(out + c * F, off, v);
+        }
+        if (owned) plane_xy();
+        else push_none();
+    }
+    if (clamped) atomicAdd(A.clamps, clamped);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+bool stage_fused_applies(const int n[3]) { return n[0] > 1 && n[1] > 1 && n[2] > 1; }
+
+int stage_default_segment(const int n[3], int tx) {
+    // enough blocks to fill the chip several times over (about 3 x 256 x 4
+    // resident blocks), segments of 16 to 64 planes (each segment re-enters
+    // 2R halo planes)
+    const int ty = 256 / tx;
+    const long long tiles = (long long)((n[0] + tx - 1) / tx) * ((n[1] + ty - 1) / ty);
+    const long long target = 4096;
+    long long nseg = (target + tiles - 1) / tiles;
+    const long long max_seg = (n[2] + 15) / 16;
+    if (nseg > max_seg) nseg = max_seg;
+    if (nseg < 1) nseg = 1;
+    int seg = (int)((n[2] + nseg - 1) / nseg);
+    if (seg > 64) seg = 64;
+    return seg;
+}
+
+template <class T>
+void stage_shape(StageGrid<T>& g, int tx, int seg) {
+    const int ty = 256 / tx;
+    if (seg < 1) seg = 1;
+    if (seg > g.n[2]) seg = g.n[2];
+    g.ntx = (g.n[0] + tx - 1) / tx;
+    g.nty = (g.n[1] + ty - 1) / ty;
+    g.seg = seg;
+    g.nseg = (g.n[2] + seg - 1) / seg;
+}
+
+template <class T, int ORDER, int TX>
+static void launch_stage_t(bool hub, const StageArgs<T>& a, dim3 grid, hipStream_t s) {
+    if (hub) stage_fused<T, ORDER, TX, true><<<grid, 256, 0, s>>>(a);
+    else stage_fused<T, ORDER, TX, false><<<grid, 256, 0, s>>>(a);
+}
+
+template <class T>
+hipError_t launch_stage(int order, int tx, bool hub, const StageArgs<T>& a, long long nblocks, hipStream_t s) {
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblocks);
+    if (order == 5) {
+        if (tx == 16) launch_stage_t<T, 5, 16>(hub, a, grid, s);
+        else if (tx == 32) launch_stage_t<T, 5, 32>(hub, a, grid, s);
+        else return hipErrorInvalidValue;
+    } else if (order == 7) {
+        // WENO7 tiles are 16 x 16 (a 32 x 8 tile has 320 halo cells per plane)
+        if (tx == 16) launch_stage_t<T, 7, 16>(hub, a, grid, s);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template void stage_shape<float>(StageGrid<float>&, int, int);
+template void stage_shape<double>(StageGrid<double>&, int, int);
+template hipError_t launch_stage<float>(int, int, bool, const StageArgs<float>&, long long, hipStream_t);
+template hipError_t launch_stage<double>(int, int, bool, const StageArgs<double>&, long long, hipStream_t);
+
+}  // namespace rh

@@ -19,8 +19,10 @@ RH_BC_PERIODIC, RH_BC_OUTFLOW, RH_BC_HUBBLE = 0, 1, 2
 RH_FIELDS_CONSERVED, RH_FIELDS_PRIMITIVE = 0, 1
 RH_KERNEL_SWEEP_X, RH_KERNEL_SWEEP_Y, RH_KERNEL_SWEEP_Z, RH_KERNEL_OTHER, RH_KERNEL_ADJOINT = 0, 1, 2, 3, 4
 RH_KERNEL_SWEEP_XY = 5
-RH_KERNEL_CLASSES = 6
-KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint", "sweep_xy")
+RH_KERNEL_STAGE = 6
+RH_KERNEL_CLASSES = 7
+KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint", "sweep_xy", "stage")
+RH_PATH_AUTO, RH_PATH_SWEEPS, RH_PATH_STAGE = 0, 1, 2
 
 
 class rh_grid_desc(ctypes.Structure):
@@ -96,6 +98,14 @@ def library():
         L.rh_batch_set_tuning.argtypes = [vp, i, i, i]
         L.rh_batch_get_tuning.argtypes = [vp, ip, ip, ip]
         L.rh_batch_autotune.argtypes = [vp, i]
+        L.rh_batch_set_path.argtypes = [vp, i]
+        L.rh_batch_get_path.argtypes = [vp, ip]
+        L.rh_batch_set_stage_tuning.argtypes = [vp, i, i]
+        L.rh_batch_get_stage_tuning.argtypes = [vp, ip, ip]
+        L.rh_set_path.argtypes = [vp, i]
+        L.rh_get_path.argtypes = [vp, ip]
+        L.rh_set_stage_tuning.argtypes = [vp, i, i]
+        L.rh_get_stage_tuning.argtypes = [vp, ip, ip]
         L.rh_batch_set_timing.argtypes = [vp, i]
         L.rh_batch_kernel_times.argtypes = [vp, dp, llp, i]
         _lib = L
@@ -409,8 +419,52 @@ def rh_batch_get_tuning(batch):
 
 
 def rh_batch_autotune(batch, reps=3):
+    """Tune the launch shape of the batch's path; returns the stage tuning
+    (tile_x, seg_z) on the fused-stage path, else the sweep tuning."""
     _check(library().rh_batch_autotune(batch, int(reps)))
+    if rh_batch_get_path(batch) == RH_PATH_STAGE:
+        return rh_batch_get_stage_tuning(batch)
     return rh_batch_get_tuning(batch)
+
+
+def rh_batch_set_path(batch, path):
+    _check(library().rh_batch_set_path(batch, int(path)))
+
+
+def rh_batch_get_path(batch):
+    a = ctypes.c_int()
+    _check(library().rh_batch_get_path(batch, ctypes.byref(a)))
+    return a.value
+
+
+def rh_batch_set_stage_tuning(batch, tile_x, seg_z):
+    _check(library().rh_batch_set_stage_tuning(batch, int(tile_x), int(seg_z)))
+
+
+def rh_batch_get_stage_tuning(batch):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(library().rh_batch_get_stage_tuning(batch, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def rh_set_path(plan, path):
+    _check(library().rh_set_path(plan, int(path)))
+
+
+def rh_get_path(plan):
+    a = ctypes.c_int()
+    _check(library().rh_get_path(plan, ctypes.byref(a)))
+    return a.value
+
+
+def rh_set_stage_tuning(plan, tile_x, seg_z):
+    _check(library().rh_set_stage_tuning(plan, int(tile_x), int(seg_z)))
+
+
+def rh_get_stage_tuning(plan):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(library().rh_get_stage_tuning(plan, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def rh_batch_set_timing(batch, enable):

@@ -29,11 +29,16 @@ def run_single(rh, spec, precision, nsteps, dt):
     return u
 
 
-def run_batch(rh, specs, precision, nsteps, dt, graph=False, tuning=None, per_call=None):
+def run_batch(rh, specs, precision, nsteps, dt, graph=False, tuning=None, per_call=None, path=None,
+              stage_tuning=None):
     b = rh.Batch(specs, precision=precision)
     b.set_primitive([sp["prim"] for sp in specs])
+    if path is not None:
+        rh.rh_batch_set_path(b.batch, path)
     if tuning:
         rh.rh_batch_set_tuning(b.batch, *tuning)
+    if stage_tuning:
+        rh.rh_batch_set_stage_tuning(b.batch, *stage_tuning)
     rh.rh_batch_set_graph(b.batch, graph)
     if per_call:
         for _ in range(nsteps // per_call):
@@ -46,14 +51,19 @@ def run_batch(rh, specs, precision, nsteps, dt, graph=False, tuning=None, per_ca
     return out, tot, cnt
 
 
+@pytest.mark.parametrize("path", ["stage", "sweeps"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("order", [5, 7])
-def test_batch_equals_single_grid_runs(precision, order):
+def test_batch_equals_single_grid_runs(precision, order, path):
+    """Both batch paths (one fused launch per stage, the default; three
+    directional sweeps per stage) give every event bitwise its single-grid
+    run (directional sweeps)."""
     rh = rh_module()
     prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
     specs = small_events(order)
     dt = specs[0]["dt"]
-    got, _, cnt = run_batch(rh, specs, prec, 3, dt)
+    got, _, cnt = run_batch(rh, specs, prec, 3, dt,
+                            path=rh.RH_PATH_STAGE if path == "stage" else rh.RH_PATH_SWEEPS)
     for sp, u in zip(specs, got):
         ref = run_single(rh, sp, prec, 3, dt)
         assert np.array_equal(u, ref), "event %d differs from its single-grid run" % sp["event"]
@@ -117,16 +127,30 @@ def test_autotune_keeps_results_bitwise():
     base, _, _ = run_batch(rh, specs, rh.RH_PREC_FP32, 2, dt)
     b = rh.Batch(specs, precision=rh.RH_PREC_FP32)
     b.set_primitive([sp["prim"] for sp in specs])
+    assert rh.rh_batch_get_path(b.batch) == rh.RH_PATH_STAGE
+    tx, sz = rh.rh_batch_autotune(b.batch, 2)
+    assert tx in (32, 16) and sz >= 1
+    b.step(dt, 2)
+    for a, c in zip(base, b.get()):
+        assert np.array_equal(a, c)
+    b.close()
+    for stuning in [(16, 3), (32, 64), (16, 1000)]:
+        got, _, _ = run_batch(rh, specs, rh.RH_PREC_FP32, 2, dt, stage_tuning=stuning)
+        for a, c in zip(base, got):
+            assert np.array_equal(a, c), stuning
+    for tuning in [(16, 8, 64), (64, 128, 16)]:
+        got, _, _ = run_batch(rh, specs, rh.RH_PREC_FP32, 2, dt, tuning=tuning, path=rh.RH_PATH_SWEEPS)
+        for a, c in zip(base, got):
+            assert np.array_equal(a, c), tuning
+    b = rh.Batch(specs, precision=rh.RH_PREC_FP32)
+    b.set_primitive([sp["prim"] for sp in specs])
+    rh.rh_batch_set_path(b.batch, rh.RH_PATH_SWEEPS)
     tx, sy, sz = rh.rh_batch_autotune(b.batch, 2)
     assert tx in (64, 32, 16) and sy >= 4 and sz >= 4
     b.step(dt, 2)
     for a, c in zip(base, b.get()):
         assert np.array_equal(a, c)
     b.close()
-    for tuning in [(16, 8, 64), (64, 128, 16)]:
-        got, _, _ = run_batch(rh, specs, rh.RH_PREC_FP32, 2, dt, tuning=tuning)
-        for a, c in zip(base, got):
-            assert np.array_equal(a, c), tuning
 
 
 def test_batch_rejects_mixed_or_degenerate_grids():
