@@ -200,6 +200,27 @@ rh_status rh_get_path(const rh_plan* plan, int* path);
 rh_status rh_set_stage_tuning(rh_plan* plan, int tile_x, int seg_z);
 rh_status rh_get_stage_tuning(const rh_plan* plan, int* tile_x, int* seg_z);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the totals of
+ * rh_totals for a state given directly, with no plan and no host transfer.
+ * state: device buffer [5][ncell] of the given precision (RH_PREC_*), ncell
+ * cells, 1 <= ncell with one field of at most RH_NOALLOC_MAX_BYTES bytes.
+ * out_dev: caller-owned device buffer of 6 doubles, receiving the FP64 sums
+ * of E, Mx, My, Mz and N (the deterministic two-pass reduction of rh_totals,
+ * so the same bits rh_totals returns for the same state) and, in out_dev[5],
+ * the number of cells with a non-finite value.  Enqueued on stream (a
+ * hipStream_t as void*, NULL = legacy default stream) of the current device;
+ * nothing is allocated: the reduction partials live in a library-owned static
+ * device array of 6 x 512 doubles (24 KiB) per GPU, whose address is looked up
+ * on the first call on each device.  Every call on one GPU shares that array,
+ * so calls that can overlap on one GPU (different streams, or threads without
+ * ordering) race; calls on one stream are ordered and safe.
+ * Errors: RH_E_INVAL (NULL pointer, unknown precision, ncell out of range),
+ * RH_E_NOTSUP (device index above 63), RH_E_HIP. */
+#define RH_NOALLOC_MAX_BYTES 4294967295LL
+rh_status rh_totals_noalloc(const void* state, int precision, long long ncell, double* out_dev,
+                            void* stream);
+
 /* Reset the floor counter reported by rh_totals to zero (asynchronous). */
 rh_status rh_reset_counters(rh_plan* plan);
 

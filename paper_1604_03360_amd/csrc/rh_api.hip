@@ -10,11 +10,19 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/rh.h"
 #include "rh_internal.hpp"
+
+// Reduction partials of rh_totals_noalloc: [6][kTotalsBlocks] doubles (24 KiB),
+// one copy per GPU, held from module load until the process ends.  Host code
+// never passes this name to a kernel or a copy (on the host it only stands in
+// for the symbol): the device address is looked up once per device with
+// hipGetSymbolAddress and that address is used instead.
+static __device__ __align__(256) double scratch[6 * rh::kTotalsBlocks];
 
 namespace {
 
@@ -27,6 +35,29 @@ rh_status fail(rh_status code, const std::string& msg) {
 
 rh_status hip_fail(hipError_t e, const char* what) {
     return fail(RH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device address of `scratch` on each device, looked up on the first
+// rh_totals_noalloc call made with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+rh_status scratch_for_current_device(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RH_E_NOTSUP, "device index beyond the library's table of 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(RH_E_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+        g_scratch_dev[dev] = (double*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return RH_OK;
 }
 
 struct TimedLaunch {
@@ -520,6 +551,23 @@ rh_status rh_totals(rh_plan* p, double out[5], long long counters[2]) {
     if (p->d.strict && (clamps > 0 || host[5] > 0.0))
         return fail(RH_E_PHYS, "strict plan: a primitive-recovery floor acted or a value is not finite");
     return RH_OK;
+}
+
+rh_status rh_totals_noalloc(const void* state, int precision, long long ncell, double* out_dev, void* stream) {
+    if (!state || !out_dev) return fail(RH_E_INVAL, "state and out_dev must not be NULL");
+    if (precision != RH_PREC_FP64 && precision != RH_PREC_FP32) return fail(RH_E_INVAL, "unknown precision");
+    const long long elem = precision == RH_PREC_FP32 ? 4 : 8;
+    if (ncell < 1 || ncell > (long long)RH_NOALLOC_MAX_BYTES / elem)
+        return fail(RH_E_INVAL, "ncell must be >= 1 and one field at most RH_NOALLOC_MAX_BYTES (4 GiB - 1) bytes");
+    double* partials = nullptr;
+    rh_status st = scratch_for_current_device(&partials);
+    if (st != RH_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const hipError_t e =
+        precision == RH_PREC_FP32
+            ? rh::launch_totals<float>((const float*)state, ncell, partials, rh::kTotalsBlocks, out_dev, s)
+            : rh::launch_totals<double>((const double*)state, ncell, partials, rh::kTotalsBlocks, out_dev, s);
+    return e == hipSuccess ? RH_OK : hip_fail(e, "totals launch");
 }
 
 rh_status rh_reset_counters(rh_plan* p) {

@@ -23,6 +23,7 @@ RH_KERNEL_STAGE = 6
 RH_KERNEL_CLASSES = 7
 KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint", "sweep_xy", "stage")
 RH_PATH_AUTO, RH_PATH_SWEEPS, RH_PATH_STAGE = 0, 1, 2
+RH_NOALLOC_MAX_BYTES = 4294967295
 
 
 class rh_grid_desc(ctypes.Structure):
@@ -106,6 +107,7 @@ def library():
         L.rh_get_path.argtypes = [vp, ip]
         L.rh_set_stage_tuning.argtypes = [vp, i, i]
         L.rh_get_stage_tuning.argtypes = [vp, ip, ip]
+        L.rh_totals_noalloc.argtypes = [vp, i, ctypes.c_longlong, vp, vp]
         L.rh_batch_set_timing.argtypes = [vp, i]
         L.rh_batch_kernel_times.argtypes = [vp, dp, llp, i]
         _lib = L
@@ -172,6 +174,11 @@ def rh_totals(plan):
     cnt = (ctypes.c_longlong * 2)()
     _check(library().rh_totals(plan, out, cnt))
     return list(out), list(cnt)
+
+
+def rh_totals_noalloc(state_ptr, precision, ncell, out_ptr, stream_ptr):
+    """Enqueue the FP64 totals of a state [5][ncell] into the device buffer out_ptr[6]."""
+    _check(library().rh_totals_noalloc(state_ptr, precision, ncell, out_ptr, stream_ptr))
 
 
 def rh_reset_counters(plan):

@@ -67,3 +67,13 @@ def test_null_plan_calls_fail_cleanly(lib):
     assert lib.rh_apply_L(None, 0.0, None) == rh.RH_E_INVAL
     assert lib.rh_state_bytes(None) == 0
     lib.rh_plan_destroy(None)
+
+
+def test_noalloc_totals_rejects_bad_arguments_without_a_gpu(lib):
+    from paper_1604_03360_amd import rh
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+    cases = [(None, rh.RH_PREC_FP64, 8, dummy), (dummy, 7, 8, dummy), (dummy, rh.RH_PREC_FP32, 0, dummy),
+             (dummy, rh.RH_PREC_FP32, rh.RH_NOALLOC_MAX_BYTES // 4 + 1, dummy), (dummy, rh.RH_PREC_FP64, 8, None)]
+    for state, prec, ncell, out in cases:
+        assert lib.rh_totals_noalloc(state, prec, ncell, out, None) == rh.RH_E_INVAL
+        assert rh.rh_last_error()
