@@ -25,6 +25,9 @@ _SRC = os.path.join(_HERE, "rh_oracle.cpp")
 _LIB = os.path.join(_HERE, "librh_oracle.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_HUBBLE = 0, 1, 2
+MUSTA = 2                      # scheme id ("order") of MUSTA-FORCE
+EOS_CONFORMAL, EOS_IDEAL = 0, 1
+LIM_MINMOD, LIM_MC, LIM_VANLEER, LIM_SUPERBEE, LIM_NONE = 0, 1, 2, 3, 4
 
 
 def build(force=False):
@@ -40,7 +43,9 @@ def build(force=False):
 class OrcGrid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("h", ctypes.c_double * 3), ("c0", ctypes.c_double * 3),
                 ("order", ctypes.c_int), ("bc", ctypes.c_int * 3), ("eps", ctypes.c_double),
-                ("hub", ctypes.c_double * 3)]
+                ("hub", ctypes.c_double * 3), ("limiter", ctypes.c_int), ("musta_k", ctypes.c_int),
+                ("musta_cfl", ctypes.c_double), ("lf_local", ctypes.c_int), ("eos", ctypes.c_int),
+                ("gamma", ctypes.c_double)]
 
 
 _lib = None
@@ -70,6 +75,13 @@ def lib():
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
         L.orc_vjp_L.argtypes = [gp, ctypes.c_double, dp, dp, dp]
+        L.orc_prim2con_eos.argtypes = [gp, ctypes.c_long, dp, dp]
+        L.orc_con2prim_eos.argtypes = [gp, ctypes.c_long, dp, dp, lp]
+        L.orc_max_speed.argtypes = [gp, ctypes.c_int, ctypes.c_long, dp, dp]
+        L.orc_limited_slope.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_limited_slope.restype = ctypes.c_double
+        L.orc_musta_flux.argtypes = [gp, ctypes.c_int, dp, dp, dp, lp]
+        L.orc_musta_face.argtypes = [gp, ctypes.c_int, dp, dp]
         L.orc_vjp_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.orc_jvp_step.argtypes = [gp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         _lib = L
@@ -94,9 +106,20 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def make_grid(shape, h, c0, order=5, bc=(BC_PERIODIC,) * 3, eps=1e-6, hub=(10.0, 1.0, 0.5)):
-    """shape = (nx, ny, nz); h = (dx, dy, dz); c0 = centre of cell (0,0,0)."""
+def make_grid(shape, h, c0, order=5, bc=(BC_PERIODIC,) * 3, eps=1e-6, hub=(10.0, 1.0, 0.5),
+              limiter=LIM_MINMOD, musta_k=2, musta_cfl=0.9, lf_local=False, eos=EOS_CONFORMAL,
+              gamma=5.0 / 3.0):
+    """shape = (nx, ny, nz); h = (dx, dy, dz); c0 = centre of cell (0,0,0).
+    order: 5 or 7 (WENO) or MUSTA (MUSTA-FORCE with the given limiter, stage
+    count and local Courant number); lf_local: WENO splitting with alpha per
+    interface; eos: EOS_CONFORMAL (p = e/3) or EOS_IDEAL (p = (gamma-1)(e-n))."""
     g = OrcGrid()
+    g.limiter = int(limiter)
+    g.musta_k = int(musta_k)
+    g.musta_cfl = float(musta_cfl)
+    g.lf_local = int(bool(lf_local))
+    g.eos = int(eos)
+    g.gamma = float(gamma)
     for a in range(3):
         g.n[a] = int(shape[a])
         g.h[a] = float(h[a])
@@ -112,7 +135,10 @@ def grid_from_spec(spec, order=None):
     """Oracle grid from a workload spec produced by the input generators."""
     return make_grid(spec["shape"], spec["h"], spec["c0"], order=order or spec.get("order", 5),
                      bc=spec["bc"], eps=spec.get("eps", 1e-6),
-                     hub=spec.get("hub", (10.0, 1.0, 0.5)))
+                     hub=spec.get("hub", (10.0, 1.0, 0.5)), limiter=spec.get("limiter", LIM_MINMOD),
+                     musta_k=spec.get("musta_k", 2), musta_cfl=spec.get("musta_cfl", 0.9),
+                     lf_local=spec.get("lf_local", False), eos=spec.get("eos", EOS_CONFORMAL),
+                     gamma=spec.get("gamma", 5.0 / 3.0))
 
 
 def prim2con(prim):
@@ -243,3 +269,54 @@ def jvp_step(grid, u, v, dt, t=0.0):
     rc = lib().orc_jvp_step(ctypes.byref(grid), float(t), float(dt), _dp(u), _dp(v), _dp(out))
     assert rc == 0
     return out
+
+
+def prim2con_eos(grid, prim):
+    """Primitive -> conserved for the grid's equation of state."""
+    prim = _f64(prim)
+    out = np.empty_like(prim)
+    rc = lib().orc_prim2con_eos(ctypes.byref(grid), prim.size // 5, _dp(prim), _dp(out))
+    assert rc == 0
+    return out
+
+
+def con2prim_eos(grid, con, return_clamps=False):
+    """Conserved -> primitive (e, v, n) for the grid's equation of state (with floors)."""
+    con = _f64(con)
+    out = np.empty_like(con)
+    cl = ctypes.c_long(0)
+    rc = lib().orc_con2prim_eos(ctypes.byref(grid), con.size // 5, _dp(con), _dp(out), ctypes.byref(cl))
+    assert rc == 0
+    return (out, cl.value) if return_clamps else out
+
+
+def max_speed(grid, d, con):
+    """Largest characteristic speed along axis d of each conserved state."""
+    con = _f64(con)
+    out = np.empty(con.size // 5)
+    rc = lib().orc_max_speed(ctypes.byref(grid), int(d), con.size // 5, _dp(con), _dp(out))
+    assert rc == 0
+    return out
+
+
+def limited_slope(limiter, a, b):
+    return lib().orc_limited_slope(int(limiter), float(a), float(b))
+
+
+def musta_flux(grid, d, uL, uR, return_clamps=False):
+    """MUSTA-FORCE flux along d between two states (5 values each)."""
+    uL, uR = _f64(uL), _f64(uR)
+    F = np.empty(5)
+    cl = ctypes.c_long(0)
+    rc = lib().orc_musta_flux(ctypes.byref(grid), int(d), _dp(uL), _dp(uR), _dp(F), ctypes.byref(cl))
+    assert rc == 0
+    return (F, cl.value) if return_clamps else F
+
+
+def musta_face(grid, d, cells):
+    """Face flux from the four cells i-1 .. i+2 around face i+1/2 (array [4][5])."""
+    cells = _f64(cells)
+    F = np.empty(5)
+    rc = lib().orc_musta_face(ctypes.byref(grid), int(d), _dp(cells), _dp(F))
+    assert rc == 0
+    return F

@@ -18,9 +18,16 @@
 //   * Sec. 1.2: finite-difference WENO of fifth and seventh order (Jiang-Shu
 //     smoothness indicators, nonlinear weights, component-wise, global
 //     Lax-Friedrichs splitting with alpha = 1).
+//   * Sec. 1.1: the MUSTA-FORCE scheme -- MUSCL reconstruction with a slope
+//     limiter, then a multi-stage predictor-corrector on the first-order
+//     centred (FORCE) flux at every interface.
 // Readings where the paper is silent (equation of state p = e/3, closed-form
-// primitive recovery, floors, boundary conditions, epsilon = 1e-6) are listed with
-// the design notes of the repository.
+// primitive recovery, floors, boundary conditions, epsilon = 1e-6, the MUSTA
+// stage count and local Courant number, the limiters offered) are listed with
+// the design notes of the repository.  Two generalisations of the flux step
+// are also implemented: local Lax-Friedrichs splitting (alpha per interface
+// from the characteristic speeds) and an ideal-gas equation of state whose
+// primitive recovery is a bisection for the speed.
 //
 // Everything is templated on the scalar type so that T = std::complex<double>
 // evaluates the same arithmetic in complex-step mode (directional derivatives for
@@ -36,6 +43,7 @@
 #include <cstring>
 #include <cstdint>
 #include <algorithm>
+#include <type_traits>
 
 using cplx = std::complex<double>;
 
@@ -48,6 +56,9 @@ inline double re(const cplx& x) { return x.real(); }
 // Grid description (the oracle's own; mirrors nothing outside this file).
 // ---------------------------------------------------------------------------
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_HUBBLE = 2 };
+enum { SCHEME_MUSTA = 2 };   // order field: 5 or 7 select WENO, 2 MUSTA-FORCE
+enum { EOS_CONFORMAL = 0, EOS_IDEAL = 1 };
+enum { LIM_MINMOD = 0, LIM_MC = 1, LIM_VANLEER = 2, LIM_SUPERBEE = 3, LIM_NONE = 4 };
 
 // Floors applied to the primitive recovery only (never to the stored state).
 const double E_FLOOR = 1e-12;      // below this energy density the cell is treated as at rest
@@ -65,6 +76,12 @@ struct orc_grid {
     int bc[3];         // per axis: 0 periodic, 1 outflow (zero gradient), 2 analytic Hubble flow
     double eps;        // WENO epsilon
     double hub[3];     // Hubble flow: t0, e0, n0
+    int limiter;       // MUSTA-FORCE: MUSCL slope limiter (LIM_*)
+    int musta_k;       // MUSTA-FORCE: FORCE evaluations per interface (>= 1)
+    double musta_cfl;  // MUSTA-FORCE: dt/dx of the local predictor-corrector
+    int lf_local;      // WENO: 0 global Lax-Friedrichs (alpha = 1), 1 alpha per interface
+    int eos;           // 0 conformal p = e/3, 1 ideal gas p = (gamma - 1)(e - n), p >= 0
+    double gamma;      // ideal gas: adiabatic index
 };
 
 }  // extern "C"
@@ -129,6 +146,189 @@ void flux(int d, const T u[5], const T v[3], T p, T f[5]) {
     f[2] = u[2] * v[d] + (d == 1 ? p : T(0.0));
     f[3] = u[3] * v[d] + (d == 2 ? p : T(0.0));
     f[4] = u[4] * v[d];
+}
+
+// ---------------------------------------------------------------------------
+// Generalised equation of state (beyond the paper's test fluids).  The ideal
+// gas has unit rest mass per unit of the conserved charge: e = n + n eps_int,
+// p = (gamma - 1) n eps_int = (gamma - 1)(e - n), cut off at zero pressure.
+// Its sound speed is c_s^2 = gamma p / (e + p) (relativistic enthalpy
+// e + p); the conformal fluid has c_s^2 = 1/3.
+// ---------------------------------------------------------------------------
+double ideal_pressure(double gamma, double e, double n) {
+    double p = (gamma - 1.0) * (e - n);
+    return p > 0.0 ? p : 0.0;
+}
+
+double eos_pressure(const orc_grid& g, double e, double n) {
+    return g.eos == EOS_IDEAL ? ideal_pressure(g.gamma, e, n) : e / 3.0;
+}
+
+double sound_speed2(const orc_grid& g, double e, double p) {
+    if (g.eos != EOS_IDEAL) return 1.0 / 3.0;
+    return e + p > 0.0 ? g.gamma * p / (e + p) : 0.0;
+}
+
+// (e, vx, vy, vz, n) -> (E, Mx, My, Mz, N) for the grid's equation of state:
+// E = (e + p) W^2 - p, M = (e + p) W^2 v, N = n W, W^2 = 1 / (1 - v^2).
+void prim2con_eos(const orc_grid& g, const double pr[5], double u[5]) {
+    double e = pr[0], vx = pr[1], vy = pr[2], vz = pr[3], n = pr[4];
+    double p = eos_pressure(g, e, n);
+    double v2 = vx * vx + vy * vy + vz * vz;
+    double W2 = 1.0 / (1.0 - v2);
+    double w = e + p;
+    u[0] = w * W2 - p;
+    u[1] = w * W2 * vx;
+    u[2] = w * W2 * vy;
+    u[3] = w * W2 * vz;
+    u[4] = n * std::sqrt(W2);
+}
+
+// Ideal-gas recovery.  With the velocity v along M, E + p = (e + p) W^2 and
+// M = (E + p) v, so e = E - |M| v and n = N sqrt(1 - v^2); the speed is the
+// root in [0, 1) of g(v) = v (E + p(e(v), n(v))) - |M|.  g(0) = -|M| <= 0,
+// g(1) = E + p - |M| > 0 below the cap, and g is increasing (dg/dv >=
+// E - (gamma - 1)|M| > 0 for gamma <= 2), so plain bisection finds it; it stops
+// when the bracket is below one part in 1e16 of the speed.  Same floors as the
+// closed form: E below the floor -> at rest; |M|^2 capped at (1 - delta) E^2.
+void con2prim_ideal(const orc_grid& g, const double u[5], double v[3], double& p, double& e,
+                    double& n, long* clamped) {
+    double E = u[0], Mx = u[1], My = u[2], Mz = u[3], N = u[4];
+    if (E < E_FLOOR) {
+        v[0] = v[1] = v[2] = 0.0;
+        e = E > 0.0 ? E : 0.0;
+        n = N;
+        p = ideal_pressure(g.gamma, e, n);
+        if (clamped) ++*clamped;
+        return;
+    }
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    double cap = (1.0 - V_DELTA) * E * E;
+    if (M2 > cap) {
+        double s = std::sqrt(cap / M2);
+        Mx *= s; My *= s; Mz *= s;
+        M2 = cap;
+        if (clamped) ++*clamped;
+    }
+    double M = std::sqrt(M2);
+    double speed = 0.0;
+    if (M > 0.0) {
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 400; ++it) {
+            double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            double pm = ideal_pressure(g.gamma, E - M * mid, N * std::sqrt(1.0 - mid * mid));
+            if (mid * (E + pm) - M < 0.0) lo = mid; else hi = mid;
+            if (hi - lo <= 1e-16 * hi) break;
+        }
+        speed = 0.5 * (lo + hi);
+    }
+    e = E - M * speed;
+    n = N * std::sqrt(1.0 - speed * speed);
+    p = ideal_pressure(g.gamma, e, n);
+    double k = M > 0.0 ? speed / M : 0.0;
+    v[0] = k * Mx;
+    v[1] = k * My;
+    v[2] = k * Mz;
+}
+
+// Primitive recovery for the grid's equation of state; T = double only for the
+// ideal gas (the complex-step paths are conformal).
+template <class T>
+void recover(const orc_grid& g, const T u[5], T v[3], T& p, T& e, T& n, long* clamped) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (g.eos == EOS_IDEAL) {
+            con2prim_ideal(g, u, v, p, e, n, clamped);
+            return;
+        }
+    }
+    con2prim(u, v, p, n, clamped);
+    e = 3.0 * p;
+}
+
+// Largest characteristic speed |lambda| of the flux along axis d: the
+// acoustic eigenvalues
+//   lambda+- = (v_d (1 - c_s^2) +- c_s sqrt((1 - v^2)(1 - v^2 c_s^2 - v_d^2 (1 - c_s^2))))
+//              / (1 - v^2 c_s^2)
+// bracket the material speed v_d, so the larger magnitude of the two is the
+// bound.
+double max_speed(const orc_grid& g, int d, const double v[3], double p, double e) {
+    double cs2 = sound_speed2(g, e, p);
+    double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double vd = v[d];
+    double disc = cs2 * (1.0 - v2) * (1.0 - v2 * cs2 - vd * vd * (1.0 - cs2));
+    double root = std::sqrt(disc > 0.0 ? disc : 0.0);
+    double den = 1.0 - v2 * cs2;
+    double lp = (vd * (1.0 - cs2) + root) / den, lm = (vd * (1.0 - cs2) - root) / den;
+    return std::max(std::fabs(lp), std::fabs(lm));
+}
+
+// ---------------------------------------------------------------------------
+// MUSTA-FORCE (Sec. 1.1).
+// MUSCL: limited slope of cell j from a = u_j - u_{j-1}, b = u_{j+1} - u_j,
+// component-wise on the conserved variables; zero where a and b do not share a
+// sign.  minmod: the smaller magnitude; MC: min(2|a|, 2|b|, |a + b|/2); van
+// Leer: 2ab/(a + b); superbee: max(min(2|a|, |b|), min(|a|, 2|b|)); NONE: no
+// slope (first order).
+// ---------------------------------------------------------------------------
+double limited_slope(int lim, double a, double b) {
+    if (lim == LIM_NONE) return 0.0;
+    if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0.0;
+    double sg = a > 0.0 ? 1.0 : -1.0, aa = std::fabs(a), ab = std::fabs(b);
+    if (lim == LIM_MINMOD) return sg * std::min(aa, ab);
+    if (lim == LIM_MC) return sg * std::min(std::min(2.0 * aa, 2.0 * ab), 0.5 * (aa + ab));
+    if (lim == LIM_VANLEER) return 2.0 * a * b / (a + b);
+    return sg * std::max(std::min(2.0 * aa, ab), std::min(aa, 2.0 * ab));
+}
+
+// physical flux along d of a state, through the grid's recovery
+void state_flux(const orc_grid& g, int d, const double u[5], double f[5], long* clamped) {
+    double v[3], p, e, n;
+    recover(g, u, v, p, e, n, clamped);
+    flux(d, u, v, p, f);
+}
+
+// The MUSTA flux at one interface from the reconstructed states uL | uR,
+// with lam = dt/dx of the local solver.  Each stage evaluates the FORCE flux,
+// the mean of the Lax-Friedrichs flux and the flux of the two-step
+// Lax-Wendroff (Richtmyer) state,
+//   uM = (uL + uR)/2 - lam/2 (fR - fL),
+//   F  = (fL + 2 f(uM) + fR)/4 - (uR - uL)/(4 lam),
+// and, before every stage but the last, opens the local Riemann fan by one
+// local time step of each side's cell: uL -= lam (F - fL), uR -= lam (fR - F).
+void musta_flux(const orc_grid& g, int d, const double uL0[5], const double uR0[5], double F[5],
+                long* clamped) {
+    double uL[5], uR[5];
+    for (int c = 0; c < 5; ++c) { uL[c] = uL0[c]; uR[c] = uR0[c]; }
+    const double lam = g.musta_cfl;
+    for (int stage = 1; stage <= g.musta_k; ++stage) {
+        double fL[5], fR[5], uM[5], fM[5];
+        state_flux(g, d, uL, fL, clamped);
+        state_flux(g, d, uR, fR, clamped);
+        for (int c = 0; c < 5; ++c) uM[c] = 0.5 * (uL[c] + uR[c]) - 0.5 * lam * (fR[c] - fL[c]);
+        state_flux(g, d, uM, fM, clamped);
+        for (int c = 0; c < 5; ++c)
+            F[c] = 0.25 * (fL[c] + 2.0 * fM[c] + fR[c]) - (uR[c] - uL[c]) / (4.0 * lam);
+        if (stage < g.musta_k) {
+            for (int c = 0; c < 5; ++c) {
+                uL[c] = uL[c] - lam * (F[c] - fL[c]);
+                uR[c] = uR[c] - lam * (fR[c] - F[c]);
+            }
+        }
+    }
+}
+
+// Face i+1/2 from the four cells i-1 .. i+2 along the line (s[0..3]): MUSCL
+// states uL = u_i + slope_i / 2, uR = u_{i+1} - slope_{i+1} / 2, then MUSTA.
+void musta_face(const orc_grid& g, int d, const double s[4][5], double F[5], long* clamped) {
+    double uL[5], uR[5];
+    for (int c = 0; c < 5; ++c) {
+        double si = limited_slope(g.limiter, s[1][c] - s[0][c], s[2][c] - s[1][c]);
+        double sj = limited_slope(g.limiter, s[2][c] - s[1][c], s[3][c] - s[2][c]);
+        uL[c] = s[1][c] + 0.5 * si;
+        uR[c] = s[2][c] - 0.5 * sj;
+    }
+    musta_flux(g, d, uL, uR, F, clamped);
 }
 
 // ---------------------------------------------------------------------------
@@ -256,14 +456,74 @@ void line_cell(const orc_grid& g, double t, const T* u, int d, int ijk[3], int m
     for (int f = 0; f < 5; ++f) out[f] = u[f * ncell + id];
 }
 
+// MUSTA-FORCE form of Eq. (2): the face fluxes of every axis longer than one
+// cell (an axis of one cell contributes nothing), accumulated x, y, z.  Two
+// ghost cells per side feed the MUSCL slopes of the faces at the line ends.
+// Floors are counted per recovery of a face state (three per MUSTA stage),
+// each face of the grid once.
+void apply_L_musta(const orc_grid& g, double t, const double* u, double* L, long* clamps) {
+    const int G = 2;
+    size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+    long clamp_total = 0;
+    for (int d = 0; d < 3; ++d) {
+        if (g.n[d] == 1) continue;
+        int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        int nd = g.n[d];
+        long nlines = (long)g.n[a1] * g.n[a2];
+#pragma omp parallel for schedule(static) reduction(+ : clamp_total)
+        for (long line = 0; line < nlines; ++line) {
+            int ijk[3];
+            ijk[d] = 0;
+            ijk[a1] = (int)(line % g.n[a1]);
+            ijk[a2] = (int)(line / g.n[a1]);
+            int len = nd + 2 * G;
+            std::vector<double> uu(5 * len), Fh(5 * (nd + 1));
+            for (int m = -G; m < nd + G; ++m) {
+                double uc[5];
+                line_cell(g, t, u, d, ijk, m, uc);
+                for (int c = 0; c < 5; ++c) uu[c * len + m + G] = uc[c];
+            }
+            for (int i = -1; i < nd; ++i) {
+                double st[4][5], F[5];
+                for (int o = 0; o < 4; ++o)
+                    for (int c = 0; c < 5; ++c) st[o][c] = uu[c * len + (i - 1 + o) + G];
+                long cl = 0;
+                musta_face(g, d, st, F, &cl);
+                clamp_total += cl;
+                for (int c = 0; c < 5; ++c) Fh[c * (nd + 1) + i + 1] = F[c];
+            }
+            for (int i = 0; i < nd; ++i) {
+                int cc[3] = {ijk[0], ijk[1], ijk[2]};
+                cc[d] = i;
+                size_t id = cidx(g, cc[0], cc[1], cc[2]);
+                for (int c = 0; c < 5; ++c) {
+                    const double* Fc = &Fh[c * (nd + 1)];   // faces -1/2 .. nd-1/2 of component c
+                    L[c * ncell + id] += (Fc[i] - Fc[i + 1]) / g.h[d];
+                }
+            }
+        }
+    }
+    if (clamps) *clamps += clamp_total;
+}
+
 // Eq. (2): L(u) = sum_d (Fhat_d(i-1/2) - Fhat_d(i+1/2)) / h_d, directions in the
-// order x, y, z, accumulated into a zeroed array.
+// order x, y, z, accumulated into a zeroed array.  WENO face fluxes from
+// Lax-Friedrichs-split fluxes f+- = (F +- alpha u)/2: alpha = 1 (global), or,
+// with lf_local, the largest characteristic speed over the 2r cells of the
+// interface's stencil.
 template <class T>
 void apply_L(const orc_grid& g, double t, const T* u, T* L, long* clamps) {
-    const int r = g.order == 5 ? 3 : 4;
-    const int G = r;  // ghost cells per side
     size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
     for (size_t q = 0; q < 5 * ncell; ++q) L[q] = T(0.0);
+    if constexpr (std::is_same<T, double>::value) {
+        if (g.order == SCHEME_MUSTA) {
+            apply_L_musta(g, t, u, L, clamps);
+            return;
+        }
+    }
+    const int r = g.order == 5 ? 3 : 4;
+    const int G = r;  // ghost cells per side
+    const bool local = g.lf_local != 0;
     long clamp_total = 0;
     for (int d = 0; d < 3; ++d) {
         int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
@@ -276,27 +536,42 @@ void apply_L(const orc_grid& g, double t, const T* u, T* L, long* clamps) {
             ijk[a1] = (int)(line % g.n[a1]);
             ijk[a2] = (int)(line / g.n[a1]);
             int len = nd + 2 * G;
-            std::vector<T> fp(5 * len), fm(5 * len), Fh(5 * (nd + 1));
+            std::vector<T> ff(5 * len), uu(5 * len), Fh(5 * (nd + 1));
+            std::vector<double> spd(len, 1.0);
             for (int m = -G; m < nd + G; ++m) {
-                T uc[5], v[3], p, nden, f[5];
+                T uc[5], v[3], p, e, nden, f[5];
                 line_cell(g, t, u, d, ijk, m, uc);
                 long cl = 0;
-                con2prim(uc, v, p, nden, &cl);
+                recover(g, uc, v, p, e, nden, &cl);
                 if (m >= 0 && m < nd) clamp_total += cl;
                 flux(d, uc, v, p, f);
-                // global Lax-Friedrichs splitting, alpha = 1
                 for (int c = 0; c < 5; ++c) {
-                    fp[c * len + m + G] = 0.5 * (f[c] + uc[c]);
-                    fm[c * len + m + G] = 0.5 * (f[c] - uc[c]);
+                    ff[c * len + m + G] = f[c];
+                    uu[c * len + m + G] = uc[c];
+                }
+                if constexpr (std::is_same<T, double>::value) {
+                    if (local) spd[m + G] = max_speed(g, d, v, p, e);
                 }
             }
             // interfaces i+1/2 for i = -1 .. nd-1 stored at Fh[i+1]
             for (int i = -1; i < nd; ++i) {
+                double alpha = 1.0;
+                if (local) {
+                    alpha = 0.0;
+                    for (int o = 0; o < 2 * r; ++o) alpha = std::max(alpha, spd[(i - r + 1 + o) + G]);
+                }
                 for (int c = 0; c < 5; ++c) {
                     T sp[7], sm[7];
                     for (int o = 0; o < 2 * r - 1; ++o) {
-                        sp[o] = fp[c * len + (i - r + 1 + o) + G];   // f+_{i-r+1+o}
-                        sm[o] = fm[c * len + (i + r - o) + G];       // mirrored: f-_{i+r-o}
+                        const int jp = c * len + (i - r + 1 + o) + G;   // f+_{i-r+1+o}
+                        const int jm = c * len + (i + r - o) + G;       // mirrored: f-_{i+r-o}
+                        if (local) {
+                            sp[o] = 0.5 * (ff[jp] + alpha * uu[jp]);
+                            sm[o] = 0.5 * (ff[jm] - alpha * uu[jm]);
+                        } else {
+                            sp[o] = 0.5 * (ff[jp] + uu[jp]);
+                            sm[o] = 0.5 * (ff[jm] - uu[jm]);
+                        }
                     }
                     Fh[c * (nd + 1) + i + 1] = weno(g.order, sp, g.eps, 0) + weno(g.order, sm, g.eps, 0);
                 }
@@ -328,12 +603,27 @@ void rk3_step(const orc_grid& g, double t, double dt, T* u, long* clamps) {
 
 bool grid_ok(const orc_grid* g) {
     if (!g) return false;
-    if (g->order != 5 && g->order != 7) return false;
+    if (g->order != 5 && g->order != 7 && g->order != SCHEME_MUSTA) return false;
     for (int a = 0; a < 3; ++a) {
         if (g->n[a] < 1 || !(g->h[a] > 0.0)) return false;
         if (g->bc[a] < 0 || g->bc[a] > 2) return false;
+        // the analytic boundary is the conformal fluid's Hubble flow
+        if (g->bc[a] == BC_HUBBLE && g->eos != EOS_CONFORMAL) return false;
+    }
+    if (g->eos != EOS_CONFORMAL && g->eos != EOS_IDEAL) return false;
+    if (g->eos == EOS_IDEAL && !(g->gamma > 1.0 && g->gamma <= 2.0)) return false;
+    if (g->lf_local != 0 && g->lf_local != 1) return false;
+    if (g->order == SCHEME_MUSTA) {
+        if (g->limiter < LIM_MINMOD || g->limiter > LIM_NONE) return false;
+        if (g->musta_k < 1 || !(g->musta_cfl > 0.0 && g->musta_cfl <= 1.0)) return false;
     }
     return true;
+}
+
+// The complex-step derivatives and the hand-written adjoint cover the paper's
+// WENO scheme with the conformal fluid and global splitting.
+bool grid_ok_adjoint(const orc_grid* g) {
+    return grid_ok(g) && g->order != SCHEME_MUSTA && g->eos == EOS_CONFORMAL && g->lf_local == 0;
 }
 
 }  // namespace
@@ -394,6 +684,70 @@ int orc_weno_parts(int order, const double* s, double* q, double* b) {
     return 0;
 }
 
+// Primitive <-> conserved maps and characteristic speeds for the equation of
+// state of grid g (conformal or ideal gas); SoA [5][n].
+int orc_prim2con_eos(const orc_grid* g, long n, const double* prim, double* con) {
+    if (!grid_ok(g)) return -1;
+    for (long i = 0; i < n; ++i) {
+        double pr[5], u[5];
+        for (int f = 0; f < 5; ++f) pr[f] = prim[f * n + i];
+        prim2con_eos(*g, pr, u);
+        for (int f = 0; f < 5; ++f) con[f * n + i] = u[f];
+    }
+    return 0;
+}
+
+int orc_con2prim_eos(const orc_grid* g, long n, const double* con, double* prim, long* clamps) {
+    if (!grid_ok(g)) return -1;
+    long cl = 0;
+    for (long i = 0; i < n; ++i) {
+        double u[5], v[3], p, e, nd;
+        for (int f = 0; f < 5; ++f) u[f] = con[f * n + i];
+        recover(*g, u, v, p, e, nd, &cl);
+        prim[0 * n + i] = e;
+        prim[1 * n + i] = v[0];
+        prim[2 * n + i] = v[1];
+        prim[3 * n + i] = v[2];
+        prim[4 * n + i] = nd;
+    }
+    if (clamps) *clamps = cl;
+    return 0;
+}
+
+// Largest characteristic speed along axis d of n conserved states.
+int orc_max_speed(const orc_grid* g, int d, long n, const double* con, double* out) {
+    if (!grid_ok(g) || d < 0 || d > 2) return -1;
+    for (long i = 0; i < n; ++i) {
+        double u[5], v[3], p, e, nd;
+        for (int f = 0; f < 5; ++f) u[f] = con[f * n + i];
+        recover(*g, u, v, p, e, nd, (long*)nullptr);
+        out[i] = max_speed(*g, d, v, p, e);
+    }
+    return 0;
+}
+
+// Limited MUSCL slope from the backward and forward differences a, b.
+double orc_limited_slope(int limiter, double a, double b) { return limited_slope(limiter, a, b); }
+
+// MUSTA flux along d between the states uL | uR (5 values each), and the face
+// flux from the four cells around the face (s[4][5], cell-major).
+int orc_musta_flux(const orc_grid* g, int d, const double* uL, const double* uR, double* F, long* clamps) {
+    if (!grid_ok(g) || g->order != SCHEME_MUSTA || d < 0 || d > 2) return -1;
+    long cl = 0;
+    musta_flux(*g, d, uL, uR, F, &cl);
+    if (clamps) *clamps = cl;
+    return 0;
+}
+
+int orc_musta_face(const orc_grid* g, int d, const double* s, double* F) {
+    if (!grid_ok(g) || g->order != SCHEME_MUSTA || d < 0 || d > 2) return -1;
+    double st[4][5];
+    for (int o = 0; o < 4; ++o)
+        for (int c = 0; c < 5; ++c) st[o][c] = s[o * 5 + c];
+    musta_face(*g, d, st, F, (long*)nullptr);
+    return 0;
+}
+
 // L(u) at time t (t only matters for analytic boundaries).  u, L: [5][nz][ny][nx].
 int orc_L(const orc_grid* g, double t, const double* u, double* L, long* clamps) {
     if (!grid_ok(g)) return -1;
@@ -441,7 +795,7 @@ int orc_hubble_prim(const double hub[3], double t, long n, const double* xyz, do
 // Directional derivative J(u) v of L at u by the complex step:
 // Jv = Im L(u + i h v) / h with h = 1e-30 (no subtractive cancellation).
 int orc_jvp_L(const orc_grid* g, double t, const double* u, const double* v, double* jv) {
-    if (!grid_ok(g)) return -1;
+    if (!grid_ok_adjoint(g)) return -1;
     const double h = 1e-30;
     size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
     std::vector<cplx> uc(N), Lc(N);
@@ -751,7 +1105,7 @@ extern "C" {
 
 // out = J(u)^T w for L at time t (fields [5][nz][ny][nx]).
 int orc_vjp_L(const orc_grid* g, double t, const double* u, const double* w, double* out) {
-    if (!grid_ok(g)) return -1;
+    if (!grid_ok_adjoint(g)) return -1;
     const size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
     for (size_t q = 0; q < N; ++q) out[q] = 0.0;
     vjp_L(*g, t, u, w, out);
@@ -764,7 +1118,7 @@ int orc_vjp_L(const orc_grid* g, double t, const double* u, const double* w, dou
 //   b0 = 1/3 b3 + 3/4 b2 + b1 + dt J(u)^T b1,  with b3 = ubar_in.
 int orc_vjp_step(const orc_grid* g, double t, double dt, const double* u, const double* ubar_in,
                  double* ubar_out) {
-    if (!grid_ok(g)) return -1;
+    if (!grid_ok_adjoint(g)) return -1;
     const size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
     std::vector<double> L(N), u1(N), u2(N), b2(N), b1(N), tmp(N);
     apply_L(*g, t, u, L.data(), (long*)nullptr);
@@ -787,7 +1141,7 @@ int orc_vjp_step(const orc_grid* g, double t, double dt, const double* u, const 
 // Directional derivative of one SSP-RK3 step by the complex step.
 int orc_jvp_step(const orc_grid* g, double t, double dt, const double* u, const double* v,
                  double* jv) {
-    if (!grid_ok(g)) return -1;
+    if (!grid_ok_adjoint(g)) return -1;
     const double h = 1e-30;
     const size_t N = 5 * (size_t)g->n[0] * g->n[1] * g->n[2];
     std::vector<cplx> uc(N);
