@@ -6,10 +6,11 @@
  * conserved densities u = (E, Mx, My, Mz, N) on a Cartesian grid.  Each right-
  * hand-side evaluation is the semi-discrete operator L(u) of Eq. (2), with the
  * half-cell fluxes given by finite-difference WENO5 or WENO7 reconstruction
- * (Sec. 1.2) of globally Lax-Friedrichs-split physical fluxes; the ODE is
- * integrated with the third-order strong-stability-preserving Runge-Kutta
- * method (Sec. 1).  The equation of state is conformal, p = e/3, and N is a
- * passive conserved charge.
+ * (Sec. 1.2) of Lax-Friedrichs-split physical fluxes, or by the MUSTA-FORCE
+ * scheme with MUSCL reconstruction (Sec. 1.1); the ODE is integrated with the
+ * third-order strong-stability-preserving Runge-Kutta method (Sec. 1).  The
+ * equation of state is conformal, p = e/3, with N a passive conserved charge
+ * (the paper's test fluids), or an ideal gas.
  *
  * Conventions shared by every call:
  *   - Fields are structure-of-arrays, [5][nz][ny][nx] with x fastest, in the
@@ -77,18 +78,54 @@ typedef int rh_status;
  * directional sweep per axis (x, y, z; the x and y sweeps fused into one launch
  * where rh_kernel_times reports RH_KERNEL_SWEEP_XY) with an L accumulator in the
  * workspace.  RH_PATH_STAGE: one launch per Runge-Kutta stage evaluating all three
- * axes of L and the stage combine (no L accumulator); it needs more than one
- * cell on every axis.  Both give bitwise the same results.  RH_PATH_AUTO (the
- * default) takes RH_PATH_SWEEPS for single grids and RH_PATH_STAGE for batches. */
+ * axes of L and the stage combine (no L accumulator).  For the WENO schemes with
+ * global splitting and the conformal fluid both give bitwise the same results;
+ * MUSTA-FORCE, local splitting and the ideal gas exist on RH_PATH_STAGE only.
+ * RH_PATH_AUTO (the default) takes RH_PATH_SWEEPS for single grids where it
+ * applies and RH_PATH_STAGE otherwise and for batches. */
 #define RH_PATH_AUTO   0
 #define RH_PATH_SWEEPS 1
 #define RH_PATH_STAGE  2
+
+/* Schemes (rh_grid_desc.scheme).  5 and 7: finite-difference WENO5 / WENO7
+ * (Sec. 1.2) of Lax-Friedrichs-split fluxes.  RH_SCHEME_MUSTA: MUSTA-FORCE
+ * (Sec. 1.1): MUSCL reconstruction of the conserved variables with a slope
+ * limiter (2 ghost cells), then at every face k stages of the FORCE flux
+ * F = (f_L + 2 f(u_M) + f_R)/4 - (u_R - u_L)/(4 lam), u_M = (u_L + u_R)/2 -
+ * lam/2 (f_R - f_L), each stage but the last followed by u_L -= lam (F - f_L),
+ * u_R -= lam (f_R - F), with lam = musta_cfl the local dt/dx over the light-speed
+ * bound.  The paper names the method and its ingredients only; the stage
+ * count, local Courant number and limiters offered are this library's
+ * reading of it. */
+#define RH_SCHEME_MUSTA 2
+
+/* MUSCL slope limiters (MUSTA-FORCE): the slope of cell j from a = u_j - u_{j-1}
+ * and b = u_{j+1} - u_j, zero where they differ in sign; NONE is first order. */
+#define RH_LIMITER_MINMOD   0  /* the smaller of |a|, |b| */
+#define RH_LIMITER_MC       1  /* min(2|a|, 2|b|, |a + b|/2) (monotonised central) */
+#define RH_LIMITER_VANLEER  2  /* 2ab/(a + b) */
+#define RH_LIMITER_SUPERBEE 3  /* max(min(2|a|, |b|), min(|a|, 2|b|)) */
+#define RH_LIMITER_NONE     4  /* no slope */
+
+/* Flux splitting of the WENO schemes.  GLOBAL: f+- = (F +- u)/2, alpha = 1 (the
+ * light-speed bound; the paper's reading).  LOCAL: f+- = (F +- alpha u)/2 per
+ * face, alpha the largest characteristic speed |lambda| over the face's 2r
+ * stencil cells, from the acoustic eigenvalues of the flux Jacobian. */
+#define RH_SPLIT_GLOBAL 0
+#define RH_SPLIT_LOCAL  1
+
+/* Equations of state.  CONFORMAL: p = e/3 (closed-form primitive recovery).
+ * IDEAL: ideal gas with unit rest mass per unit charge, p = (gamma - 1)(e - n),
+ * never below 0, c_s^2 = gamma p / (e + p); primitive recovery by a bracketed
+ * FP64 Newton iteration for the speed.  HUBBLE boundaries need CONFORMAL. */
+#define RH_EOS_CONFORMAL 0
+#define RH_EOS_IDEAL     1
 
 typedef struct rh_grid_desc {
     int nx, ny, nz;          /* cells per axis, each >= 1 */
     double dx, dy, dz;       /* cell widths, > 0 */
     double x0, y0, z0;       /* position of the centre of cell (0,0,0) (used by HUBBLE) */
-    int scheme;              /* 5 (WENO5, 3 ghost cells) or 7 (WENO7, 4 ghost cells) */
+    int scheme;              /* 5 (WENO5, 3 ghost cells), 7 (WENO7, 4 ghost cells) or RH_SCHEME_MUSTA */
     int precision;           /* RH_PREC_FP64 or RH_PREC_FP32 */
     int bc[3];               /* RH_BC_* for the x, y and z axes */
     double weno_eps;         /* epsilon of the nonlinear weights; 0 selects 1e-6 */
@@ -96,6 +133,12 @@ typedef struct rh_grid_desc {
     double hubble_e0;        /* HUBBLE only: e at tau = t0 */
     double hubble_n0;        /* HUBBLE only: n at tau = t0 */
     int strict;              /* nonzero: rh_totals reports RH_E_PHYS when a floor acted */
+    int limiter;             /* RH_SCHEME_MUSTA: RH_LIMITER_* (0 = minmod) */
+    int musta_stages;        /* RH_SCHEME_MUSTA: FORCE evaluations per face, 1 .. 8; 0 selects 2 */
+    double musta_cfl;        /* RH_SCHEME_MUSTA: local dt/dx of the stages, (0, 1]; 0 selects 0.9 */
+    int flux_split;          /* WENO: RH_SPLIT_GLOBAL (0) or RH_SPLIT_LOCAL */
+    int eos;                 /* RH_EOS_CONFORMAL (0) or RH_EOS_IDEAL */
+    double eos_gamma;        /* RH_EOS_IDEAL: adiabatic index in (1, 2]; 0 selects 5/3 */
 } rh_grid_desc;
 
 typedef struct rh_plan rh_plan;
@@ -108,10 +151,14 @@ const char* rh_last_error(void);
 const char* rh_version(void);
 
 /* Create a plan for one grid (Eq. (2) on a Cartesian grid).  Validates the
- * description (axes of 1 .. 2^24 cells, one field below 4 GiB) and allocates
- * only small plan-owned device memory (counters and reduction partials).  *out
- * receives the plan; it is NULL on failure.
- * Errors: RH_E_INVAL (bad description), RH_E_NOMEM, RH_E_HIP. */
+ * description (axes of 1 .. 2^24 cells, one field below 4 GiB, the scheme and
+ * its parameters) and allocates only small plan-owned device memory (counters
+ * and reduction partials).  *out receives the plan; it is NULL on failure.
+ * Floors (rh_totals counters[0]) are counted per cell and evaluation of L for
+ * WENO, and per recovery of a face state (three per MUSTA stage, each face of
+ * the grid once) for MUSTA-FORCE.
+ * Errors: RH_E_INVAL (bad description), RH_E_NOTSUP (HUBBLE boundaries with the
+ * ideal gas), RH_E_NOMEM, RH_E_HIP. */
 rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* desc);
 
 /* Release a plan and its own device memory (after waiting for the plan's work
@@ -135,14 +182,15 @@ rh_status rh_bind(rh_plan* plan, void* state, void* workspace, void* stream);
 
 /* Write the bound state from FP64 device fields src[5][nz][ny][nx] of the given
  * kind.  PRIMITIVE input is converted to conserved variables in FP64
- * (E = (e+p) g^2 - p, M = (e+p) g^2 v, N = n g, g = 1/sqrt(1-v^2)) and then
- * rounded to the plan precision.  Asynchronous.
+ * (E = (e+p) g^2 - p, M = (e+p) g^2 v, N = n g, g = 1/sqrt(1-v^2), p from the
+ * plan's equation of state) and then rounded to the plan precision.  Asynchronous.
  * Errors: RH_E_STATE (unbound), RH_E_INVAL (kind). */
 rh_status rh_set_fields(rh_plan* plan, const double* src, int kind);
 
 /* Read the bound state into FP64 device fields dst[5][nz][ny][nx].  PRIMITIVE
- * output runs the FP64 closed-form primitive recovery for p = e/3 (the same
- * recovery as the sweeps).  Asynchronous. Errors: RH_E_STATE, RH_E_INVAL. */
+ * output runs the plan's FP64 primitive recovery (closed form for p = e/3,
+ * Newton for the ideal gas; the same recovery as the kernels).  Asynchronous.
+ * Errors: RH_E_STATE, RH_E_INVAL. */
 rh_status rh_get_fields(rh_plan* plan, double* dst, int kind);
 
 /* Evaluate L(u) of Eq. (2) for the bound state at physical time t (t matters
@@ -185,18 +233,19 @@ rh_status rh_set_graph(rh_plan* plan, int enable);
 /* Select the evaluation path (RH_PATH_*) of every later call that evaluates L
  * (rh_apply_L, rh_step, rh_step_store and the stage recomputation of
  * rh_step_vjp).  Drops a captured step graph.
- * Errors: RH_E_INVAL (unknown path), RH_E_NOTSUP (RH_PATH_STAGE on a grid with
- * an axis of one cell). */
+ * Errors: RH_E_INVAL (unknown path), RH_E_NOTSUP (RH_PATH_SWEEPS for MUSTA-FORCE,
+ * local splitting or the ideal gas). */
 rh_status rh_set_path(rh_plan* plan, int path);
 
 /* The path the plan's evaluations take now (RH_PATH_SWEEPS or RH_PATH_STAGE). */
 rh_status rh_get_path(const rh_plan* plan, int* path);
 
 /* Launch shape of the fused stage: tile_x (16, or 32 for WENO5) cells along x by 256/tile_x
- * along y per block, and the z segment each block rolls along (seg_z >= 1;
- * 0 selects a default for the grid, clamped to nz).  Drops a captured step
- * graph.  rh_get_stage_tuning reports the shape in use (the segment resolved).
- * Errors: RH_E_INVAL. */
+ * along y per block (MUSTA-FORCE: 16 x 15), and the z segment each block rolls
+ * along (seg_z >= 1; 0 selects a default for the grid, clamped to nz).  Drops a
+ * captured step graph.  rh_get_stage_tuning reports the shape in use (the
+ * segment resolved).  Errors: RH_E_INVAL, RH_E_NOTSUP (tile_x 32 for WENO7 or
+ * MUSTA-FORCE). */
 rh_status rh_set_stage_tuning(rh_plan* plan, int tile_x, int seg_z);
 rh_status rh_get_stage_tuning(const rh_plan* plan, int* tile_x, int* seg_z);
 
@@ -239,6 +288,8 @@ rh_status rh_kernel_times(rh_plan* plan, double* ms_out, long long* launches_out
  * Jacobians needed to differentiate a run with respect to its initial state.
  * The derivative is that of the discrete scheme actually computed, including
  * the WENO nonlinear weights (Sec. 1.2) and the primitive-recovery floors.
+ * They cover the WENO schemes with the conformal fluid and global splitting
+ * (RH_E_NOTSUP otherwise).
  * ------------------------------------------------------------------------ */
 
 /* out = J(u)^T w, J = dL/du of Eq. (2) at state u and time t.  u, w and out are
@@ -289,8 +340,9 @@ rh_status rh_step_vjp_stored(rh_plan* plan, double t, double dt, const void* u_n
 typedef struct rh_batch rh_batch;
 
 /* Create a batch of n_grids independent grids.  All descriptions must share
- * scheme and precision and have at least 2 cells on every axis (RH_E_NOTSUP
- * otherwise).  Each grid's state occupies elements [offset_g, offset_g +
+ * scheme, precision, equation of state (and gamma), flux splitting and the
+ * MUSTA-FORCE parameters (RH_E_INVAL otherwise) and have at least 2 cells on
+ * every axis (RH_E_NOTSUP otherwise).  Each grid's state occupies elements [offset_g, offset_g +
  * 5*ncell_g) of one concatenated buffer, in the single-grid layout
  * [5][nz][ny][nx]; offsets are multiples of 64 elements. */
 rh_status rh_batch_create(rh_batch** out, int n_grids, const rh_grid_desc* descs);

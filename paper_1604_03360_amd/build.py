@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librh.so")
-SOURCES = ["rh_kernels.hip", "rh_stage.hip", "rh_adjoint.hip", "rh_api.hip"]
+SOURCES = ["rh_kernels.hip", "rh_stage.hip", "rh_musta.hip", "rh_adjoint.hip", "rh_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -176,16 +176,51 @@ void fill_stage_grid(rh::StageGrid<T>& g, const rh_grid_desc& d, long long off, 
     g.t0 = d.hubble_t0;
     g.e0 = d.hubble_e0;
     g.n0 = d.hubble_n0;
-    rh::stage_shape<T>(g, tx, seg);
+    g.gm1 = d.eos == RH_EOS_IDEAL ? d.eos_gamma - 1.0 : 0.0;
+    g.limiter = d.limiter;
+    g.mk = d.musta_stages;
+    g.lam = (T)d.musta_cfl;
+    if (d.scheme == RH_SCHEME_MUSTA) {
+        const int n[3] = {d.nx, d.ny, d.nz};
+        rh::musta_shape<T>(g, seg > 0 ? seg : rh::musta_default_segment(n));
+    } else {
+        rh::stage_shape<T>(g, tx, seg);
+    }
+}
+
+// Descriptions resolved for the kernels: defaults of the optional fields filled in.
+void resolve_desc(rh_grid_desc& d) {
+    if (d.scheme == RH_SCHEME_MUSTA) {
+        if (d.musta_stages == 0) d.musta_stages = 2;
+        if (d.musta_cfl == 0.0) d.musta_cfl = 0.9;
+    }
+    if (d.eos == RH_EOS_IDEAL && d.eos_gamma == 0.0) d.eos_gamma = 5.0 / 3.0;
+}
+
+double eos_gm1(const rh_grid_desc& d) { return d.eos == RH_EOS_IDEAL ? d.eos_gamma - 1.0 : 0.0; }
+
+// Features only the fused stage implements: MUSTA-FORCE, local splitting and
+// the ideal gas.
+bool needs_stage(const rh_grid_desc& d) {
+    return d.scheme == RH_SCHEME_MUSTA || d.flux_split == RH_SPLIT_LOCAL || d.eos == RH_EOS_IDEAL;
+}
+
+// The adjoint covers the paper's WENO scheme with the conformal fluid and
+// global splitting.
+bool adjoint_supported(const rh_grid_desc& d) { return !needs_stage(d); }
+
+// Launch one fused-stage evaluation of the scheme of d over nblocks blocks.
+template <class T>
+hipError_t launch_stage_of(const rh_grid_desc& d, int tx, bool hub, const rh::StageArgs<T>& sa,
+                           long long nblocks, hipStream_t s) {
+    if (d.scheme == RH_SCHEME_MUSTA) return rh::launch_musta<T>(hub, d.eos, sa, nblocks, s);
+    return rh::launch_stage<T>(d.scheme, tx, hub, d.flux_split == RH_SPLIT_LOCAL, d.eos, sa, nblocks, s);
 }
 
 // Path of a single grid's evaluations: the fused stage where it is requested
-// and applies; RH_PATH_AUTO keeps the directional sweeps.
-bool use_stage(const rh_plan* p) {
-    const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
-    if (!rh::stage_fused_applies(n)) return false;
-    return p->path == RH_PATH_STAGE;
-}
+// or where only it implements the scheme; RH_PATH_AUTO keeps the directional
+// sweeps otherwise.
+bool use_stage(const rh_plan* p) { return needs_stage(p->d) || p->path == RH_PATH_STAGE; }
 
 // One evaluation of L at time t on `us`; stage == 0 stores L in `lacc`,
 // otherwise the stage combine writes `uout` from `us`, `u0` and dt.
@@ -224,11 +259,14 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
         sa.t = t;
         sa.clamps = p->d_clamps;
         sa.ngrid = 0;
+        const bool musta = p->d.scheme == RH_SCHEME_MUSTA;
         fill_stage_grid<T>(sa.one, p->d, 0, p->stage_tx,
-                           p->stage_seg > 0 ? p->stage_seg : rh::stage_default_segment(n, p->stage_tx));
+                           p->stage_seg > 0 ? p->stage_seg
+                                            : (musta ? rh::musta_default_segment(n)
+                                                     : rh::stage_default_segment(n, p->stage_tx)));
         const long long nb = rh::stage_blocks(sa.one);
         return timed_launch(p, RH_KERNEL_STAGE, [&] {
-            return rh::launch_stage<T>(p->d.scheme, p->stage_tx, any_hubble(p), sa, nb, p->stream);
+            return launch_stage_of<T>(p->d, p->stage_tx, any_hubble(p), sa, nb, p->stream);
         }, "stage launch");
     }
     int i0 = 0;
@@ -361,10 +399,27 @@ rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* d) {
     }
     if (n[0] > (1 << 24) || n[1] > (1 << 24) || n[2] > (1 << 24))
         return fail(RH_E_INVAL, "axis longer than 2^24 cells");
-    if (d->scheme != 5 && d->scheme != 7) return fail(RH_E_INVAL, "scheme must be 5 or 7");
+    const bool musta = d->scheme == RH_SCHEME_MUSTA;
+    if (d->scheme != 5 && d->scheme != 7 && !musta)
+        return fail(RH_E_INVAL, "scheme must be 5, 7 or RH_SCHEME_MUSTA");
     if (d->precision != RH_PREC_FP64 && d->precision != RH_PREC_FP32)
         return fail(RH_E_INVAL, "unknown precision");
     if (d->weno_eps < 0.0) return fail(RH_E_INVAL, "weno_eps must be >= 0");
+    if (d->eos != RH_EOS_CONFORMAL && d->eos != RH_EOS_IDEAL) return fail(RH_E_INVAL, "unknown equation of state");
+    if (d->eos == RH_EOS_IDEAL && !(d->eos_gamma == 0.0 || (d->eos_gamma > 1.0 && d->eos_gamma <= 2.0)))
+        return fail(RH_E_INVAL, "eos_gamma must lie in (1, 2] (0 selects 5/3)");
+    if (d->flux_split != RH_SPLIT_GLOBAL && d->flux_split != RH_SPLIT_LOCAL)
+        return fail(RH_E_INVAL, "unknown flux splitting");
+    if (musta && d->flux_split != RH_SPLIT_GLOBAL)
+        return fail(RH_E_INVAL, "flux splitting applies to the WENO schemes only");
+    if (musta) {
+        if (d->limiter < RH_LIMITER_MINMOD || d->limiter > RH_LIMITER_NONE)
+            return fail(RH_E_INVAL, "unknown slope limiter");
+        if (d->musta_stages < 0 || d->musta_stages > 8)
+            return fail(RH_E_INVAL, "musta_stages must lie in 1..8 (0 selects 2)");
+        if (!(d->musta_cfl == 0.0 || (d->musta_cfl > 0.0 && d->musta_cfl <= 1.0)))
+            return fail(RH_E_INVAL, "musta_cfl must lie in (0, 1] (0 selects 0.9)");
+    }
     const long long ny_nz = (long long)n[1] * n[2];
     if ((ny_nz + 3) / 4 > 65535LL * 64 && n[0] > 1) return fail(RH_E_INVAL, "grid too large");
     if ((long long)(n[1] + 3) / 4 > 65535 || (long long)(n[2] + 3) / 4 > 65535)
@@ -372,6 +427,8 @@ rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* d) {
     for (int a = 0; a < 3; ++a) {
         if (d->bc[a] == RH_BC_HUBBLE && !(d->hubble_t0 > 0.0))
             return fail(RH_E_INVAL, "HUBBLE boundaries need hubble_t0 > 0");
+        if (d->bc[a] == RH_BC_HUBBLE && d->eos != RH_EOS_CONFORMAL)
+            return fail(RH_E_NOTSUP, "HUBBLE boundaries are the conformal fluid's analytic flow");
     }
     // the sweeps address one field with 32-bit byte offsets
     const long long field_bytes = (long long)n[0] * n[1] * n[2] * (d->precision == RH_PREC_FP32 ? 4 : 8);
@@ -379,7 +436,8 @@ rh_status rh_plan_create(rh_plan** out, const rh_grid_desc* d) {
     rh_plan* p = new (std::nothrow) rh_plan();
     if (!p) return fail(RH_E_NOMEM, "host allocation failed");
     p->d = *d;
-    p->ghosts = (d->scheme + 1) / 2;
+    resolve_desc(p->d);
+    p->ghosts = musta ? 2 : (d->scheme + 1) / 2;
     p->ncell = (long long)n[0] * n[1] * n[2];
     p->elem = d->precision == RH_PREC_FP32 ? 4 : 8;
     hipError_t e;
@@ -432,8 +490,10 @@ rh_status rh_set_fields(rh_plan* p, const double* src, int kind) {
     if (!src) return fail(RH_E_INVAL, "src is NULL");
     if (kind != RH_FIELDS_CONSERVED && kind != RH_FIELDS_PRIMITIVE) return fail(RH_E_INVAL, "bad kind");
     return timed_launch(p, RH_KERNEL_OTHER, [&] {
-        return is_fp32(p) ? rh::launch_set_fields<float>((float*)p->state, src, kind, p->ncell, p->stream)
-                          : rh::launch_set_fields<double>((double*)p->state, src, kind, p->ncell, p->stream);
+        return is_fp32(p) ? rh::launch_set_fields<float>((float*)p->state, src, kind, p->ncell, p->d.eos,
+                                                         eos_gm1(p->d), p->stream)
+                          : rh::launch_set_fields<double>((double*)p->state, src, kind, p->ncell, p->d.eos,
+                                                          eos_gm1(p->d), p->stream);
     }, "set_fields launch");
 }
 
@@ -444,9 +504,9 @@ rh_status rh_get_fields(rh_plan* p, double* dst, int kind) {
     if (kind != RH_FIELDS_CONSERVED && kind != RH_FIELDS_PRIMITIVE) return fail(RH_E_INVAL, "bad kind");
     return timed_launch(p, RH_KERNEL_OTHER, [&] {
         return is_fp32(p) ? rh::launch_get_fields<float>((const float*)p->state, dst, kind, p->ncell,
-                                                         p->d_clamps, p->stream)
+                                                         p->d_clamps, p->d.eos, eos_gm1(p->d), p->stream)
                           : rh::launch_get_fields<double>((const double*)p->state, dst, kind, p->ncell,
-                                                          p->d_clamps, p->stream);
+                                                          p->d_clamps, p->d.eos, eos_gm1(p->d), p->stream);
     }, "get_fields launch");
 }
 
@@ -490,9 +550,8 @@ rh_status rh_set_path(rh_plan* p, int path) {
     if (!p) return fail(RH_E_INVAL, "plan is NULL");
     if (path != RH_PATH_AUTO && path != RH_PATH_SWEEPS && path != RH_PATH_STAGE)
         return fail(RH_E_INVAL, "unknown path");
-    const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
-    if (path == RH_PATH_STAGE && !rh::stage_fused_applies(n))
-        return fail(RH_E_NOTSUP, "the fused stage needs more than one cell on every axis");
+    if (path == RH_PATH_SWEEPS && needs_stage(p->d))
+        return fail(RH_E_NOTSUP, "MUSTA-FORCE, local splitting and the ideal gas run on the fused stage only");
     p->path = path;
     drop_graph(p);
     return RH_OK;
@@ -507,7 +566,7 @@ rh_status rh_get_path(const rh_plan* p, int* path) {
 rh_status rh_set_stage_tuning(rh_plan* p, int tile_x, int seg_z) {
     if (!p) return fail(RH_E_INVAL, "plan is NULL");
     if (tile_x != 16 && tile_x != 32) return fail(RH_E_INVAL, "tile_x must be 16 or 32");
-    if (tile_x == 32 && p->d.scheme == 7) return fail(RH_E_NOTSUP, "WENO7 stage tiles are 16 cells wide");
+    if (tile_x == 32 && p->d.scheme != 5) return fail(RH_E_NOTSUP, "WENO7 and MUSTA-FORCE stage tiles are 16 cells wide");
     if (seg_z < 0) return fail(RH_E_INVAL, "seg_z must be >= 0 (0 = default)");
     p->stage_tx = tile_x;
     p->stage_seg = seg_z;
@@ -520,7 +579,8 @@ rh_status rh_get_stage_tuning(const rh_plan* p, int* tile_x, int* seg_z) {
     const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
     if (tile_x) *tile_x = p->stage_tx;
     if (seg_z) *seg_z = p->stage_seg > 0 ? (p->stage_seg < n[2] ? p->stage_seg : n[2])
-                                         : rh::stage_default_segment(n, p->stage_tx);
+                                         : (p->d.scheme == RH_SCHEME_MUSTA ? rh::musta_default_segment(n)
+                                                                           : rh::stage_default_segment(n, p->stage_tx));
     return RH_OK;
 }
 
@@ -766,7 +826,7 @@ rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T
         sa.grids = (const rh::StageGrid<T>*)b->d_stage;
         sa.ngrid = b->ngrid;
         return batch_timed(b, s, RH_KERNEL_STAGE, [&] {
-            return rh::launch_stage<T>(b->scheme, b->stage_tx, b->any_hubble, sa, b->stage_nblocks, s);
+            return launch_stage_of<T>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, s);
         }, "batched stage launch");
     }
     rh::BatchArgs<T> B;
@@ -880,9 +940,16 @@ rh_status rh_batch_create(rh_batch** out, int n_grids, const rh_grid_desc* descs
             return st;
         }
         rh_plan_destroy(probe);
-        if (d.scheme != b->scheme || d.precision != b->precision) {
+        rh_grid_desc r = d, r0 = descs[0];
+        resolve_desc(r);
+        resolve_desc(r0);
+        if (r.scheme != r0.scheme || r.precision != r0.precision || r.eos != r0.eos ||
+            (r.eos == RH_EOS_IDEAL && r.eos_gamma != r0.eos_gamma) || r.flux_split != r0.flux_split ||
+            (r.scheme == RH_SCHEME_MUSTA && (r.limiter != r0.limiter || r.musta_stages != r0.musta_stages ||
+                                             r.musta_cfl != r0.musta_cfl))) {
             delete b;
-            return fail(RH_E_INVAL, "all grids of a batch must share scheme and precision");
+            return fail(RH_E_INVAL, "all grids of a batch must share scheme, precision, equation of state, "
+                                    "flux splitting and the MUSTA-FORCE parameters");
         }
         if (d.nx < 2 || d.ny < 2 || d.nz < 2) {
             delete b;
@@ -890,7 +957,7 @@ rh_status rh_batch_create(rh_batch** out, int n_grids, const rh_grid_desc* descs
         }
         for (int a = 0; a < 3; ++a)
             if (d.bc[a] == RH_BC_HUBBLE) b->any_hubble = true;
-        b->d.push_back(d);
+        b->d.push_back(r);
         b->off[i] = acc;
         const long long n = 5LL * d.nx * d.ny * d.nz;
         acc += (n + 63) / 64 * 64;
@@ -968,8 +1035,10 @@ rh_status rh_batch_set_fields(rh_batch* b, const double* src, int kind) {
     for (int i = 0; i < b->ngrid; ++i) {
         const long long n = (long long)b->d[i].nx * b->d[i].ny * b->d[i].nz;
         hipError_t e = b->precision == RH_PREC_FP32
-            ? rh::launch_set_fields<float>((float*)b->state + b->off[i], src + b->off[i], kind, n, b->stream)
-            : rh::launch_set_fields<double>((double*)b->state + b->off[i], src + b->off[i], kind, n, b->stream);
+            ? rh::launch_set_fields<float>((float*)b->state + b->off[i], src + b->off[i], kind, n, b->d[i].eos,
+                                           eos_gm1(b->d[i]), b->stream)
+            : rh::launch_set_fields<double>((double*)b->state + b->off[i], src + b->off[i], kind, n, b->d[i].eos,
+                                            eos_gm1(b->d[i]), b->stream);
         if (e != hipSuccess) return hip_fail(e, "set_fields launch");
     }
     return RH_OK;
@@ -984,9 +1053,9 @@ rh_status rh_batch_get_fields(rh_batch* b, double* dst, int kind) {
         const long long n = (long long)b->d[i].nx * b->d[i].ny * b->d[i].nz;
         hipError_t e = b->precision == RH_PREC_FP32
             ? rh::launch_get_fields<float>((const float*)b->state + b->off[i], dst + b->off[i], kind, n,
-                                           b->d_clamps, b->stream)
+                                           b->d_clamps, b->d[i].eos, eos_gm1(b->d[i]), b->stream)
             : rh::launch_get_fields<double>((const double*)b->state + b->off[i], dst + b->off[i], kind, n,
-                                            b->d_clamps, b->stream);
+                                            b->d_clamps, b->d[i].eos, eos_gm1(b->d[i]), b->stream);
         if (e != hipSuccess) return hip_fail(e, "get_fields launch");
     }
     return RH_OK;
@@ -1063,6 +1132,8 @@ rh_status rh_batch_set_path(rh_batch* b, int path) {
     if (!b) return fail(RH_E_INVAL, "batch is NULL");
     if (path != RH_PATH_AUTO && path != RH_PATH_SWEEPS && path != RH_PATH_STAGE)
         return fail(RH_E_INVAL, "unknown path");
+    if (path == RH_PATH_SWEEPS && needs_stage(b->d[0]))
+        return fail(RH_E_NOTSUP, "MUSTA-FORCE, local splitting and the ideal gas run on the fused stage only");
     b->path = path;
     drop_graph(b);
     return RH_OK;
@@ -1077,7 +1148,7 @@ rh_status rh_batch_get_path(const rh_batch* b, int* path) {
 rh_status rh_batch_set_stage_tuning(rh_batch* b, int tile_x, int seg_z) {
     if (!b) return fail(RH_E_INVAL, "batch is NULL");
     if (tile_x != 16 && tile_x != 32) return fail(RH_E_INVAL, "tile_x must be 16 or 32");
-    if (tile_x == 32 && b->scheme == 7) return fail(RH_E_NOTSUP, "WENO7 stage tiles are 16 cells wide");
+    if (tile_x == 32 && b->scheme != 5) return fail(RH_E_NOTSUP, "WENO7 and MUSTA-FORCE stage tiles are 16 cells wide");
     if (seg_z < 1) return fail(RH_E_INVAL, "seg_z must be >= 1");
     b->stage_tx = tile_x;
     b->stage_seg = seg_z;
@@ -1171,7 +1242,7 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
                     sa.clamps = b->d_clamps;
                     sa.grids = (const rh::StageGrid<float>*)b->d_stage;
                     sa.ngrid = b->ngrid;
-                    er = rh::launch_stage<float>(b->scheme, b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
+                    er = launch_stage_of<float>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
                 } else {
                     rh::StageArgs<double> sa;
                     std::memset(&sa, 0, sizeof(sa));
@@ -1182,7 +1253,7 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
                     sa.clamps = b->d_clamps;
                     sa.grids = (const rh::StageGrid<double>*)b->d_stage;
                     sa.ngrid = b->ngrid;
-                    er = rh::launch_stage<double>(b->scheme, b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
+                    er = launch_stage_of<double>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
                 }
                 return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
             };
@@ -1200,7 +1271,7 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
         float bms = 1e30f;
         rh_status rs = RH_OK;
         for (int tx : {16, 32}) {
-            if (tx == 32 && b->scheme == 7) continue;
+            if (tx == 32 && b->scheme != 5) continue;
             for (int sg : {16, 24, 32, 48, 64}) {
                 b->stage_tx = tx;
                 b->stage_seg = sg;
@@ -1410,6 +1481,8 @@ extern "C" {
 rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void* out) {
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
+    if (!adjoint_supported(p->d))
+        return fail(RH_E_NOTSUP, "the adjoint covers the WENO schemes with the conformal fluid and global splitting");
     if (!u || !w || !out) return fail(RH_E_INVAL, "NULL buffer");
     const size_t sb = rh_state_bytes(p);
     if (overlaps(out, sb, u, sb) || overlaps(out, sb, w, sb)) return fail(RH_E_INVAL, "out aliases u or w");
@@ -1441,6 +1514,8 @@ rh_status rh_step_vjp_stored(rh_plan* p, double t, double dt, const void* u_n, c
                              const void* ubar_in, void* ubar_out, void* scratch) {
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
+    if (!adjoint_supported(p->d))
+        return fail(RH_E_NOTSUP, "the adjoint covers the WENO schemes with the conformal fluid and global splitting");
     if (!u_n || !stages || !ubar_in || !ubar_out || !scratch) return fail(RH_E_INVAL, "NULL buffer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
     const size_t sb = rh_state_bytes(p);
@@ -1472,6 +1547,8 @@ rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const vo
                       void* ubar_out, void* scratch) {
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
+    if (!adjoint_supported(p->d))
+        return fail(RH_E_NOTSUP, "the adjoint covers the WENO schemes with the conformal fluid and global splitting");
     if (!u_n || !ubar_in || !ubar_out || !scratch) return fail(RH_E_INVAL, "NULL buffer");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
     const size_t sb = rh_state_bytes(p);

@@ -171,6 +171,90 @@ __device__ __forceinline__ void recover_kp3(double E, double Mx, double My, doub
     p = (E2 - M2) * a * r;
 }
 
+// Ideal-gas equation of state (unit rest mass per unit charge):
+// p = (gamma - 1)(e - n), cut off at zero pressure; c_s^2 = gamma p / (e + p).
+__device__ __forceinline__ double ideal_p(double gm1, double e, double n) {
+    const double p = gm1 * (e - n);
+    return p > 0.0 ? p : 0.0;
+}
+
+// Ideal-gas primitive recovery (FP64), in the form of recover_kp3: v_d =
+// kap * Ms_d, with e and p.  The speed v along M solves
+//   g(v) = v (E + p(E - |M| v, N sqrt(1 - v^2))) - |M| = 0,
+// g increasing on [0, 1) (dg/dv >= E - (gamma - 1)|M| > 0 for gamma <= 2), with
+// the root inside [|M| / (gamma E), |M| / E] because 0 <= p <= (gamma - 1) E.
+// Newton steps from the upper end, kept inside the shrinking bracket (a step
+// leaving it is replaced by bisection), stop at a relative change of 1e-15.
+// Floors as the closed form: E below the floor -> at rest; |M|^2 capped.
+__device__ inline void recover_ideal(double E, double Mx, double My, double Mz, double N, double gm1,
+                                     double& kap, double& Mxs, double& Mys, double& Mzs, double& p,
+                                     double& e, unsigned& clamped) {
+    if (E < kEFloor) {
+        kap = 0.0;
+        Mxs = Mys = Mzs = 0.0;
+        e = E > 0.0 ? E : 0.0;
+        p = ideal_p(gm1, e, N);
+        ++clamped;
+        return;
+    }
+    double M2 = Mx * Mx + My * My + Mz * Mz;
+    const double cap = (1.0 - kVDelta) * E * E;
+    Mxs = Mx;
+    Mys = My;
+    Mzs = Mz;
+    if (M2 > cap) {
+        const double sc = sqrt(cap / M2);
+        Mxs *= sc;
+        Mys *= sc;
+        Mzs *= sc;
+        M2 = cap;
+        ++clamped;
+    }
+    if (!(M2 > 0.0)) {
+        kap = 0.0;
+        e = E;
+        p = ideal_p(gm1, E, N);
+        return;
+    }
+    const double M = sqrt(M2);
+    double lo = M / ((gm1 + 1.0) * E), hi = M / E, v = hi;
+#pragma unroll 1
+    for (int it = 0; it < 80; ++it) {
+        const double w = sqrt(1.0 - v * v);
+        const double pr = gm1 * ((E - M * v) - N * w);
+        double g, dg;
+        if (pr > 0.0) {
+            g = v * (E + pr) - M;
+            dg = (E + pr) + v * gm1 * (N * v / w - M);
+        } else {
+            g = v * E - M;
+            dg = E;
+        }
+        if (g == 0.0) break;
+        if (g > 0.0) hi = v;
+        else lo = v;
+        double vn = v - g / dg;
+        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
+        const double dv = fabs(vn - v);
+        v = vn;
+        if (dv <= 1e-15 * v) break;
+    }
+    kap = v / M;
+    e = E - M * v;
+    p = ideal_p(gm1, e, N * sqrt(1.0 - v * v));
+}
+
+// Largest characteristic speed along an axis, from the velocity along it, v^2
+// and c_s^2: the acoustic eigenvalues
+//   (v_d (1 - c^2) +- c sqrt((1 - v^2)(1 - v^2 c^2 - v_d^2 (1 - c^2)))) / (1 - v^2 c^2)
+// bracket v_d, so the larger magnitude of the two bounds every wave.
+__device__ __forceinline__ double max_char_speed(double vd, double v2, double cs2) {
+    const double disc = cs2 * (1.0 - v2) * (1.0 - v2 * cs2 - vd * vd * (1.0 - cs2));
+    const double root = sqrt(disc > 0.0 ? disc : 0.0);
+    const double a = vd * (1.0 - cs2);
+    return (fabs(a) + root) / (1.0 - v2 * cs2);
+}
+
 // Split fluxes f+- = (F_d(u) +- u) / 2 of one cell along axis DIR, given the
 // velocity along DIR and the pressure, returned doubled (F_d +- u).
 //

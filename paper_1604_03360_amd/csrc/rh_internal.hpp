@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "rh_device.hpp"
+#include "../../include/rh.h"
 
 namespace rh {
 
@@ -11,6 +12,9 @@ namespace rh {
 //   0: write L (accumulated over the directions done so far) to `lacc`;
 //   1..3: fuse the SSP-RK3 stage combine and write the new state to `uout`.
 enum { STAGE_WRITE_L = 0, STAGE_1 = 1, STAGE_2 = 2, STAGE_3 = 3 };
+
+// Equations of state of the kernels (the values of RH_EOS_*).
+enum { EOS_CONFORMAL = 0, EOS_IDEAL = 1 };
 
 template <class T>
 struct SweepArgs {
@@ -110,11 +114,13 @@ template <class T>
 hipError_t launch_sweep_batch(int dir, int order, int tx, const BatchArgs<T>& b, int nblocks,
                               hipStream_t s);
 void batch_blocks(const int n[3], int tx, const int seg[3], int blocks[3], int nchunk[3]);
+// Field conversion for the equation of state eos (EOS_*; gm1 = gamma - 1 of the ideal gas).
 template <class T>
-hipError_t launch_set_fields(T* state, const double* src, int kind, long long ncell, hipStream_t s);
+hipError_t launch_set_fields(T* state, const double* src, int kind, long long ncell, int eos, double gm1,
+                             hipStream_t s);
 template <class T>
 hipError_t launch_get_fields(const T* state, double* dst, int kind, long long ncell,
-                             unsigned* clamps, hipStream_t s);
+                             unsigned* clamps, int eos, double gm1, hipStream_t s);
 template <class T>
 hipError_t launch_totals(const T* state, long long ncell, double* partials, int nblk,
                          double* out, hipStream_t s);
@@ -151,6 +157,10 @@ struct StageGrid {
     int blk0;               // first (logical) block of this grid
     double c0[3], h[3];     // cell-0 centre and widths (analytic boundaries)
     double t0, e0, n0;      // analytic boundary parameters
+    double gm1;             // ideal gas: gamma - 1 (unused for the conformal fluid)
+    int limiter;            // MUSTA-FORCE: MUSCL slope limiter (RH_LIMITER_*)
+    int mk;                 // MUSTA-FORCE: FORCE evaluations per face
+    T lam;                  // MUSTA-FORCE: dt/dx of the local predictor-corrector
 };
 
 template <class T>
@@ -176,14 +186,57 @@ template <class T>
 long long stage_blocks(const StageGrid<T>& g) {
     return (long long)g.ntx * g.nty * g.nseg;
 }
-// True where the fused stage applies (every axis longer than one cell).
-bool stage_fused_applies(const int n[3]);
 // Launch the fused stage over nblocks blocks (tile width tx in {16, 32}); hub
-// selects the instantiation with analytic (HUBBLE) ghost cells.
+// selects the instantiation with analytic (HUBBLE) ghost cells, local the
+// Lax-Friedrichs splitting with alpha per interface, eos the equation of state.
 template <class T>
-hipError_t launch_stage(int order, int tx, bool hub, const StageArgs<T>& a, long long nblocks, hipStream_t s);
+hipError_t launch_stage(int order, int tx, bool hub, bool local, int eos, const StageArgs<T>& a,
+                        long long nblocks, hipStream_t s);
 // Default z segment of the fused stage for a grid of n cells (tiles of tx).
 int stage_default_segment(const int n[3], int tx);
+
+// MUSTA-FORCE stage (the same work items, with x-y tiles of kMustaTX x
+// kMustaTY cells): one launch evaluates the MUSCL + MUSTA face fluxes of x, y
+// and z and applies the stage combine.
+constexpr int kMustaTX = 16, kMustaTY = 15;
+template <class T>
+void musta_shape(StageGrid<T>& g, int seg);
+int musta_default_segment(const int n[3]);
+template <class T>
+hipError_t launch_musta(bool hub, int eos, const StageArgs<T>& a, long long nblocks, hipStream_t s);
+
+// The chip hands consecutive blocks of a launch to its eight XCDs in turn
+// (block b to XCD b mod 8).  Renumbering gives every XCD a contiguous range of
+// logical blocks, so tiles that share halo cells meet in the same L2.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+// Grid of a fused-stage block: binary search of the block table sorted by
+// first block (ngrid > 0), or the single grid.
+template <class T>
+__device__ __forceinline__ int stage_grid_of(const StageArgs<T>& A, int b) {
+    int g = 0;
+    if (A.ngrid > 0) {
+        int lo = 0, hi = A.ngrid - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.grids[mid].blk0 <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        g = lo;
+    }
+    return g;
+}
+
+__device__ __forceinline__ int ghost_index(int m, int nd, int bc) {
+    if (bc == RH_BC_PERIODIC) {
+        m %= nd;
+        return m < 0 ? m + nd : m;
+    }
+    return m < 0 ? 0 : nd - 1;   // outflow: zero-gradient copy of the edge cell
+}
 
 // Load / store through a uniform base pointer and a 32-bit byte offset (the
 // plan limits one field to < 4 GiB), so that address arithmetic stays 32-bit
@@ -195,6 +248,44 @@ __device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
 template <class T>
 __device__ __forceinline__ void st_off(T* base, uint32_t off, T v) {
     *(T*)((char*)base + off) = v;
+}
+
+// State of cell (x, y, z) of grid G, of which at most one coordinate lies
+// outside the grid; ghost cells follow the boundary condition of that axis
+// (analytic ones are evaluated at the stage time t).  The analytic branch is
+// compiled only where HUB is set: inlined into a rolling loop its FP64
+// temporaries cost about 30 registers per lane even when never taken.
+template <class T, bool HUB>
+__device__ __forceinline__ void stage_load(const StageGrid<T>& G, const T* us, long long F, double t,
+                                           int x, int y, int z, T u[5]) {
+    bool analytic = false;
+    if (x < 0 || x >= G.n[0]) {
+        if (HUB && G.bc[0] == RH_BC_HUBBLE) analytic = true;
+        else x = ghost_index(x, G.n[0], G.bc[0]);
+    }
+    if (y < 0 || y >= G.n[1]) {
+        if (HUB && G.bc[1] == RH_BC_HUBBLE) analytic = true;
+        else y = ghost_index(y, G.n[1], G.bc[1]);
+    }
+    if (z < 0 || z >= G.n[2]) {
+        if (HUB && G.bc[2] == RH_BC_HUBBLE) analytic = true;
+        else z = ghost_index(z, G.n[2], G.bc[2]);
+    }
+    if (HUB && analytic) {
+        HubbleBC hb;
+        hb.t = t;
+        hb.t0 = G.t0;
+        hb.e0 = G.e0;
+        hb.n0 = G.n0;
+        double uh[5];
+        hubble_conserved(hb, G.c0[0] + x * G.h[0], G.c0[1] + y * G.h[1], G.c0[2] + z * G.h[2], uh);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f] = (T)uh[f];
+        return;
+    }
+    const uint32_t off = (uint32_t)sizeof(T) * ((uint32_t)x + (uint32_t)G.n[0] * ((uint32_t)y + (uint32_t)G.n[1] * (uint32_t)z));
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = ld_off(us + f * F, off);
 }
 
 }  // namespace rh

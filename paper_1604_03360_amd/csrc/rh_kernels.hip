@@ -460,14 +460,39 @@ __device__ inline void cons_to_prim(const double u[5], double pr[5], unsigned& c
     pr[4] = N * sqrt(1.0 - k * k * M2);
 }
 
+// Ideal gas: primitive -> conserved with p = (gamma - 1)(e - n), and the
+// Newton recovery back.
+__device__ inline void prim_to_cons_ideal(const double pr[5], double gm1, double u[5]) {
+    const double e = pr[0], vx = pr[1], vy = pr[2], vz = pr[3], nn = pr[4];
+    const double p = ideal_p(gm1, e, nn);
+    const double g2 = 1.0 / (1.0 - (vx * vx + vy * vy + vz * vz));
+    const double w = e + p;
+    u[0] = w * g2 - p;
+    u[1] = w * g2 * vx;
+    u[2] = w * g2 * vy;
+    u[3] = w * g2 * vz;
+    u[4] = nn * sqrt(g2);
+}
+
+__device__ inline void cons_to_prim_ideal(const double u[5], double gm1, double pr[5], unsigned& clamped) {
+    double kap, Mxs, Mys, Mzs, p, e;
+    recover_ideal(u[0], u[1], u[2], u[3], u[4], gm1, kap, Mxs, Mys, Mzs, p, e, clamped);
+    pr[0] = e;
+    pr[1] = kap * Mxs;
+    pr[2] = kap * Mys;
+    pr[3] = kap * Mzs;
+    pr[4] = u[4] * sqrt(1.0 - (pr[1] * pr[1] + pr[2] * pr[2] + pr[3] * pr[3]));
+}
+
 template <class T>
-__global__ void set_fields_kernel(T* state, const double* src, int kind, long long n) {
+__global__ void set_fields_kernel(T* state, const double* src, int kind, long long n, int eos, double gm1) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         double a[5], u[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) a[f] = src[f * n + i];
-        if (kind == RH_FIELDS_PRIMITIVE) prim_to_cons(a, u);
+        if (kind == RH_FIELDS_PRIMITIVE && eos == EOS_IDEAL) prim_to_cons_ideal(a, gm1, u);
+        else if (kind == RH_FIELDS_PRIMITIVE) prim_to_cons(a, u);
         else {
 #pragma unroll
             for (int f = 0; f < 5; ++f) u[f] = a[f];
@@ -479,14 +504,15 @@ __global__ void set_fields_kernel(T* state, const double* src, int kind, long lo
 
 template <class T>
 __global__ void get_fields_kernel(const T* state, double* dst, int kind, long long n,
-                                  unsigned* clamps) {
+                                  unsigned* clamps, int eos, double gm1) {
     unsigned clamped = 0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         double u[5], o[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) u[f] = (double)state[f * n + i];
-        if (kind == RH_FIELDS_PRIMITIVE) cons_to_prim(u, o, clamped);
+        if (kind == RH_FIELDS_PRIMITIVE && eos == EOS_IDEAL) cons_to_prim_ideal(u, gm1, o, clamped);
+        else if (kind == RH_FIELDS_PRIMITIVE) cons_to_prim(u, o, clamped);
         else {
 #pragma unroll
             for (int f = 0; f < 5; ++f) o[f] = u[f];
@@ -840,15 +866,16 @@ hipError_t launch_combine(const SweepArgs<T>& a, hipStream_t s) {
 }
 
 template <class T>
-hipError_t launch_set_fields(T* state, const double* src, int kind, long long n, hipStream_t s) {
-    set_fields_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(state, src, kind, n);
+hipError_t launch_set_fields(T* state, const double* src, int kind, long long n, int eos, double gm1,
+                             hipStream_t s) {
+    set_fields_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(state, src, kind, n, eos, gm1);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_get_fields(const T* state, double* dst, int kind, long long n, unsigned* clamps,
-                             hipStream_t s) {
-    get_fields_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(state, dst, kind, n, clamps);
+                             int eos, double gm1, hipStream_t s) {
+    get_fields_kernel<T><<<elementwise_blocks(n), 256, 0, s>>>(state, dst, kind, n, clamps, eos, gm1);
     return hipGetLastError();
 }
 
@@ -863,9 +890,10 @@ hipError_t launch_totals(const T* state, long long n, double* partials, int nblk
 #define RH_INSTANTIATE(T)                                                                         \
     template hipError_t launch_sweep<T>(int, int, const SweepArgs<T>&, hipStream_t);               \
     template hipError_t launch_combine<T>(const SweepArgs<T>&, hipStream_t);                       \
-    template hipError_t launch_set_fields<T>(T*, const double*, int, long long, hipStream_t);      \
-    template hipError_t launch_get_fields<T>(const T*, double*, int, long long, unsigned*,         \
+    template hipError_t launch_set_fields<T>(T*, const double*, int, long long, int, double,       \
                                              hipStream_t);                                         \
+    template hipError_t launch_get_fields<T>(const T*, double*, int, long long, unsigned*, int,    \
+                                             double, hipStream_t);                                 \
     template hipError_t launch_totals<T>(const T*, long long, double*, int, double*, hipStream_t); \
     template hipError_t launch_sweep_batch<T>(int, int, int, const BatchArgs<T>&, int, hipStream_t); \
     template hipError_t launch_sweep_xy<T>(int, SweepArgs<T>, T, hipStream_t);

@@ -20,66 +20,19 @@
 //
 // Ensembles use the same kernel: each block finds its grid in a table sorted
 // by first block, so one launch covers every grid of the batch.
+//
+// Two generalisations of the flux step are instantiated here as well: local
+// Lax-Friedrichs splitting (LOCAL: the block stages the physical flux and the
+// state of each cell with its largest characteristic speed, and every face
+// reconstructs F +- alpha u with alpha the largest speed of its 2R stencil
+// cells), and the ideal-gas equation of state (EOS_IDEAL: Newton recovery of
+// the speed).  An axis of one cell contributes nothing to L.
 #include "rh_internal.hpp"
 #include "../../include/rh.h"
 
 namespace rh {
 
 namespace {
-
-// The chip hands consecutive blocks of a launch to its eight XCDs in turn
-// (block b to XCD b mod 8).  Renumbering gives every XCD a contiguous range of
-// logical blocks, so tiles that share halo cells meet in the same L2.
-__device__ __forceinline__ int xcd_logical(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + min(x, r) + i;
-}
-
-__device__ __forceinline__ int ghost_index(int m, int nd, int bc) {
-    if (bc == RH_BC_PERIODIC) {
-        m %= nd;
-        return m < 0 ? m + nd : m;
-    }
-    return m < 0 ? 0 : nd - 1;   // outflow: zero-gradient copy of the edge cell
-}
-
-// State of cell (x, y, z) of grid G, of which at most one coordinate lies
-// outside the grid; ghost cells follow the boundary condition of that axis
-// (analytic ones are evaluated at the stage time t).  The analytic branch is
-// compiled only where HUB is set: inlined into the rolling loop its FP64
-// temporaries cost about 30 registers per lane even when never taken.
-template <class T, bool HUB>
-__device__ __forceinline__ void stage_load(const StageGrid<T>& G, const T* us, long long F, double t,
-                                           int x, int y, int z, T u[5]) {
-    bool analytic = false;
-    if (x < 0 || x >= G.n[0]) {
-        if (HUB && G.bc[0] == RH_BC_HUBBLE) analytic = true;
-        else x = ghost_index(x, G.n[0], G.bc[0]);
-    }
-    if (y < 0 || y >= G.n[1]) {
-        if (HUB && G.bc[1] == RH_BC_HUBBLE) analytic = true;
-        else y = ghost_index(y, G.n[1], G.bc[1]);
-    }
-    if (z < 0 || z >= G.n[2]) {
-        if (HUB && G.bc[2] == RH_BC_HUBBLE) analytic = true;
-        else z = ghost_index(z, G.n[2], G.bc[2]);
-    }
-    if (HUB && analytic) {
-        HubbleBC hb;
-        hb.t = t;
-        hb.t0 = G.t0;
-        hb.e0 = G.e0;
-        hb.n0 = G.n0;
-        double uh[5];
-        hubble_conserved(hb, G.c0[0] + x * G.h[0], G.c0[1] + y * G.h[1], G.c0[2] + z * G.h[2], uh);
-#pragma unroll
-        for (int f = 0; f < 5; ++f) u[f] = (T)uh[f];
-        return;
-    }
-    const uint32_t off = (uint32_t)sizeof(T) * ((uint32_t)x + (uint32_t)G.n[0] * ((uint32_t)y + (uint32_t)G.n[1] * (uint32_t)z));
-#pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = ld_off(us + f * F, off);
-}
 
 // One reconstruction from a window of 2R doubled split fluxes of cells
 // i - R + 1 .. i + R (interface i + 1/2): plus = left-biased on f+, minus =
@@ -99,36 +52,77 @@ __device__ __forceinline__ T stage_recon_minus(const T* w, T eps2) {
 }  // namespace
 
 // Minimum resident blocks per CU (= waves per SIMD) for the register budget;
-// FP64 blocks other than WENO5 16 x 16 need more than half of the 160 KB LDS.
-template <class T, int ORDER, int TX>
+// FP64 blocks other than WENO5 16 x 16 with global splitting need more than
+// half of the 160 KB LDS.
+template <class T, int ORDER, int TX, bool LOCAL>
 struct StageMinBlocks {
-    static constexpr int value = sizeof(T) == 4 ? 3 : (ORDER == 5 && TX == 16 ? 2 : 1);
+    static constexpr int value = sizeof(T) == 4 ? 3 : (ORDER == 5 && TX == 16 && !LOCAL ? 2 : 1);
 };
 
-template <class T, int ORDER, int TX, bool HUB>
-__global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) stage_fused(StageArgs<T> A) {
+// Per-cell quantities of the stage for the fluid of EOS: v_d = kap * Ms_d,
+// pressure, and (for the local splitting) c_s^2 and the energy density.
+template <int EOS>
+__device__ __forceinline__ void stage_recover(const double u[5], double gm1, double& kap, double& Mxs,
+                                              double& Mys, double& Mzs, double& p, double& cs2,
+                                              unsigned& clamped) {
+    if constexpr (EOS == EOS_CONFORMAL) {
+        recover_kp3(u[0], u[1], u[2], u[3], kap, Mxs, Mys, Mzs, p, clamped);
+        cs2 = 1.0 / 3.0;
+    } else {
+        double e;
+        recover_ideal(u[0], u[1], u[2], u[3], u[4], gm1, kap, Mxs, Mys, Mzs, p, e, clamped);
+        cs2 = e + p > 0.0 ? (gm1 + 1.0) * p / (e + p) : 0.0;
+    }
+}
+
+// One face from the staged pairs of its 2R stencil cells: global splitting
+// stages (F + u, F - u) and reconstructs them directly; local splitting stages
+// (F, u) and reconstructs F +- alpha u with alpha the largest speed of the 2R
+// cells.
+template <class T, int ORDER>
+__device__ __forceinline__ T recon_local(const T* wa, const T* wb, T alpha, T eps2) {
+    constexpr int W = ORDER + 1;
+    T wp[W], wm[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        wp[j] = wa[j] + alpha * wb[j];
+        wm[j] = wa[j] - alpha * wb[j];
+    }
+    return stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
+}
+
+template <class T, int DIR, bool LOCAL>
+__device__ __forceinline__ void stage_pair(const T u[5], T v, T P, T a[5], T b[5]) {
+    if constexpr (LOCAL) {
+        a[0] = u[1 + DIR];
+        a[1] = u[1] * v + (DIR == 0 ? P : (T)0);
+        a[2] = u[2] * v + (DIR == 1 ? P : (T)0);
+        a[3] = u[3] * v + (DIR == 2 ? P : (T)0);
+        a[4] = u[4] * v;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) b[c] = u[c];
+    } else {
+        split_flux_vp<T, DIR>(u, v, P, a, b);
+    }
+}
+
+template <class T, int ORDER, int TX, bool HUB, bool LOCAL, int EOS>
+__global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::value)) stage_fused(StageArgs<T> A) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R, TY = 256 / TX;
     static_assert(W * (TX + TY) <= 256, "one halo cell per lane and plane");
     static_assert(5 * (TX + TY) <= 256, "one edge face (all components) per lane");
     constexpr int SX = TX + 2 * R;            // staged x row: R ghosts, TX cells, R ghosts
     constexpr int SY = TY + 2 * R;
-    __shared__ T sx[2][5][TY][SX];            // doubled x split fluxes (plus, minus)
-    __shared__ T sy[2][5][SY][TX];            // doubled y split fluxes
+    constexpr int SPX = LOCAL ? TY : 1, SPY = LOCAL ? SY : 1;
+    __shared__ T sx[2][5][TY][SX];            // doubled x split fluxes (plus, minus), or (F, u) with LOCAL
+    __shared__ T sy[2][5][SY][TX];            // the same along y
+    __shared__ T ssx[SPX][LOCAL ? SX : 1];    // LOCAL: largest speed along x of the staged cells
+    __shared__ T ssy[SPY][LOCAL ? TX : 1];    // LOCAL: largest speed along y
     __shared__ T fx[5][TY][TX + 1];           // x face fluxes: column 0 = left face of the tile, 1 + i = right face of cell i
     __shared__ T fy[5][TY + 1][TX];           // y face fluxes: row 0 = lower face of the tile, 1 + j = upper face of row j
 
     const int b = xcd_logical((int)blockIdx.x, (int)gridDim.x);
-    int g = 0;
-    if (A.ngrid > 0) {
-        int lo = 0, hi = A.ngrid - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (A.grids[mid].blk0 <= b) lo = mid;
-            else hi = mid - 1;
-        }
-        g = lo;
-    }
-    const StageGrid<T> G = A.ngrid > 0 ? A.grids[g] : A.one;
+    const StageGrid<T> G = A.ngrid > 0 ? A.grids[stage_grid_of(A, b)] : A.one;
     const int lb = b - G.blk0;
     const int tpp = G.ntx * G.nty;
     const int zs = lb / tpp, rem = lb - zs * tpp;
@@ -142,6 +136,8 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
     const T* u0 = A.u0 + G.off;
     T* out = A.out + G.off;
     const double t = A.t;
+    // an axis of one cell contributes nothing to L
+    const bool dox = nx > 1, doy = ny > 1, doz = nz > 1;
 
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
     const bool act = lx < xa && ly < ya;
@@ -185,9 +181,11 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
 
     const T eps2 = (T)4 * G.eps;   // epsilon of the doubled split fluxes
     const T hxinv = (T)0.5 * G.inv_h[0], hyinv = (T)0.5 * G.inv_h[1], hzinv = (T)0.5 * G.inv_h[2];
+    const double gm1 = G.gm1;
     unsigned clamped = 0;
 
-    T zp[5][W], zm[5][W];     // z window: doubled split fluxes of cells k - R .. k + R - 1
+    T zp[5][W], zm[5][W];     // z window: staged pairs of cells k - R .. k + R - 1
+    T zsp[LOCAL ? W : 1];     // LOCAL: their largest speeds along z
     T ring[R][5];             // x + y part of L of the last R owned planes, oldest first
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
@@ -196,17 +194,23 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
 #pragma unroll
         for (int j = 0; j < R; ++j) ring[j][c] = (T)0;
     }
+#pragma unroll
+    for (int j = 0; j < (LOCAL ? W : 1); ++j) zsp[j] = (T)0;
 
     // Enter plane m: recover the own cell, shift its z split fluxes into the
     // window and, for an owned plane, stage the x / y split fluxes of the own
     // and halo cells.
     auto enter = [&](int m, const T u[5], const T hu[5], bool owned) {
-        double kap, Mxs, Mys, Mzs, p;
+        double kap, Mxs, Mys, Mzs, p, cs2;
         unsigned c0 = 0;
-        recover_kp3((double)u[0], (double)u[1], (double)u[2], (double)u[3], kap, Mxs, Mys, Mzs, p, c0);
+        {
+            const double ud[5] = {(double)u[0], (double)u[1], (double)u[2], (double)u[3], (double)u[4]};
+            stage_recover<EOS>(ud, gm1, kap, Mxs, Mys, Mzs, p, cs2, c0);
+        }
         const T P = (T)p;
+        const double v2 = LOCAL ? kap * kap * (Mxs * Mxs + Mys * Mys + Mzs * Mzs) : 0.0;
         T fp[5], fm[5];
-        split_flux_vp<T, 2>(u, (T)(kap * Mzs), P, fp, fm);
+        stage_pair<T, 2, LOCAL>(u, (T)(kap * Mzs), P, fp, fm);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
 #pragma unroll
@@ -217,40 +221,61 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
             zp[c][W - 1] = fp[c];
             zm[c][W - 1] = fm[c];
         }
+        if constexpr (LOCAL) {
+#pragma unroll
+            for (int j = 0; j < W - 1; ++j) zsp[j] = zsp[j + 1];
+            zsp[W - 1] = (T)max_char_speed(kap * Mzs, v2, cs2);
+        }
         if (!owned) return;
         if (act) {
             clamped += c0;   // floors counted once per owned cell and evaluation of L
-            split_flux_vp<T, 0>(u, (T)(kap * Mxs), P, fp, fm);
+            stage_pair<T, 0, LOCAL>(u, (T)(kap * Mxs), P, fp, fm);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 sx[0][c][ly][R + lx] = fp[c];
                 sx[1][c][ly][R + lx] = fm[c];
             }
-            split_flux_vp<T, 1>(u, (T)(kap * Mys), P, fp, fm);
+            stage_pair<T, 1, LOCAL>(u, (T)(kap * Mys), P, fp, fm);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 sy[0][c][R + ly][lx] = fp[c];
                 sy[1][c][R + ly][lx] = fm[c];
             }
+            if constexpr (LOCAL) {
+                ssx[ly][R + lx] = (T)max_char_speed(kap * Mxs, v2, cs2);
+                ssy[R + ly][lx] = (T)max_char_speed(kap * Mys, v2, cs2);
+            }
         }
         if (hkind) {
-            double hk, hMx, hMy, hp;
+            double hk, hMx, hMy, hMz, hp, hcs2;
             unsigned hcl = 0;
-            recover_kp((double)hu[0], (double)hu[1], (double)hu[2], (double)hu[3], hk, hMx, hMy, hp, hcl);
+            {
+                const double hd[5] = {(double)hu[0], (double)hu[1], (double)hu[2], (double)hu[3], (double)hu[4]};
+                if constexpr (EOS == EOS_CONFORMAL && !LOCAL) {
+                    recover_kp(hd[0], hd[1], hd[2], hd[3], hk, hMx, hMy, hp, hcl);
+                    hMz = 0.0;
+                    hcs2 = 0.0;
+                } else {
+                    stage_recover<EOS>(hd, gm1, hk, hMx, hMy, hMz, hp, hcs2, hcl);
+                }
+            }
+            const double hv2 = LOCAL ? hk * hk * (hMx * hMx + hMy * hMy + hMz * hMz) : 0.0;
             if (hkind == 1) {
-                split_flux_vp<T, 0>(hu, (T)(hk * hMx), (T)hp, fp, fm);
+                stage_pair<T, 0, LOCAL>(hu, (T)(hk * hMx), (T)hp, fp, fm);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     sx[0][c][hr][hc] = fp[c];
                     sx[1][c][hr][hc] = fm[c];
                 }
+                if constexpr (LOCAL) ssx[hr][hc] = (T)max_char_speed(hk * hMx, hv2, hcs2);
             } else {
-                split_flux_vp<T, 1>(hu, (T)(hk * hMy), (T)hp, fp, fm);
+                stage_pair<T, 1, LOCAL>(hu, (T)(hk * hMy), (T)hp, fp, fm);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     sy[0][c][hr][hc] = fp[c];
                     sy[1][c][hr][hc] = fm[c];
                 }
+                if constexpr (LOCAL) ssy[hr][hc] = (T)max_char_speed(hk * hMy, hv2, hcs2);
             }
         }
     };
@@ -259,28 +284,58 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
     auto plane_xy = [&]() {
         __syncthreads();
         if (act) {
+            T ax = (T)0, ay = (T)0;
+            if constexpr (LOCAL) {
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    ax = max(ax, ssx[ly][lx + 1 + j]);
+                    ay = max(ay, ssy[ly + 1 + j][lx]);
+                }
+            }
             // one component at a time: unrolled, the LDS reads of all five
             // windows would be hoisted and raise the register peak
 #pragma unroll 1
             for (int c = 0; c < 5; ++c) {
                 // window of face x + 1/2: staged columns lx + 1 .. lx + 2R
-                fx[c][ly][lx + 1] = stage_recon_plus<T, ORDER>(&sx[0][c][ly][lx + 1], eps2) +
-                                    stage_recon_minus<T, ORDER>(&sx[1][c][ly][lx + 1], eps2);
+                if constexpr (LOCAL) {
+                    T wa[W], wb[W];
+#pragma unroll
+                    for (int j = 0; j < W; ++j) {
+                        wa[j] = sx[0][c][ly][lx + 1 + j];
+                        wb[j] = sx[1][c][ly][lx + 1 + j];
+                    }
+                    fx[c][ly][lx + 1] = recon_local<T, ORDER>(wa, wb, ax, eps2);
+                } else {
+                    fx[c][ly][lx + 1] = stage_recon_plus<T, ORDER>(&sx[0][c][ly][lx + 1], eps2) +
+                                        stage_recon_minus<T, ORDER>(&sx[1][c][ly][lx + 1], eps2);
+                }
                 T wp[W], wm[W];
 #pragma unroll
                 for (int j = 0; j < W; ++j) {
                     wp[j] = sy[0][c][ly + 1 + j][lx];
                     wm[j] = sy[1][c][ly + 1 + j][lx];
                 }
-                fy[c][ly + 1][lx] = stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
+                if constexpr (LOCAL) fy[c][ly + 1][lx] = recon_local<T, ORDER>(wp, wm, ay, eps2);
+                else fy[c][ly + 1][lx] = stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
             }
         }
         // faces on the lower edges of the tile, one (line, component) per lane:
         // 5 ya x jobs (window at staged column 0), then 5 xa y jobs (staged row 0)
         if (tid < 5 * ya) {
             const int r = tid / 5, c = tid - 5 * r;
-            fx[c][r][0] = stage_recon_plus<T, ORDER>(&sx[0][c][r][0], eps2) +
-                          stage_recon_minus<T, ORDER>(&sx[1][c][r][0], eps2);
+            if constexpr (LOCAL) {
+                T wa[W], wb[W], al = (T)0;
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    wa[j] = sx[0][c][r][j];
+                    wb[j] = sx[1][c][r][j];
+                    al = max(al, ssx[r][j]);
+                }
+                fx[c][r][0] = recon_local<T, ORDER>(wa, wb, al, eps2);
+            } else {
+                fx[c][r][0] = stage_recon_plus<T, ORDER>(&sx[0][c][r][0], eps2) +
+                              stage_recon_minus<T, ORDER>(&sx[1][c][r][0], eps2);
+            }
         } else if (tid < 5 * (ya + xa)) {
             const int s = tid - 5 * ya, col = s / 5, c = s - 5 * col;
             T wp[W], wm[W];
@@ -289,7 +344,14 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
                 wp[j] = sy[0][c][j][col];
                 wm[j] = sy[1][c][j][col];
             }
-            fy[c][0][col] = stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
+            if constexpr (LOCAL) {
+                T al = (T)0;
+#pragma unroll
+                for (int j = 0; j < W; ++j) al = max(al, ssy[j][col]);
+                fy[c][0][col] = recon_local<T, ORDER>(wp, wm, al, eps2);
+            } else {
+                fy[c][0][col] = stage_recon_plus<T, ORDER>(wp, eps2) + stage_recon_minus<T, ORDER>(wm, eps2);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -298,8 +360,8 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
             for (int c = 0; c < 5; ++c) ring[j][c] = ring[j + 1][c];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            const T Lx = (fx[c][ly][lx] - fx[c][ly][lx + 1]) * hxinv;
-            const T Ly = (fy[c][ly][lx] - fy[c][ly + 1][lx]) * hyinv;
+            const T Lx = dox ? (fx[c][ly][lx] - fx[c][ly][lx + 1]) * hxinv : (T)0;
+            const T Ly = doy ? (fy[c][ly][lx] - fy[c][ly + 1][lx]) * hyinv : (T)0;
             ring[R - 1][c] = Lx + Ly;
         }
     };
@@ -308,6 +370,17 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
         for (int j = 0; j < R - 1; ++j)
 #pragma unroll
             for (int c = 0; c < 5; ++c) ring[j][c] = ring[j + 1][c];
+    };
+    // z face above the window's centre, component c
+    auto zface = [&](int c) {
+        if constexpr (LOCAL) {
+            T al = (T)0;
+#pragma unroll
+            for (int j = 0; j < W; ++j) al = max(al, zsp[j]);
+            return recon_local<T, ORDER>(zp[c], zm[c], al, eps2);
+        } else {
+            return stage_recon_plus<T, ORDER>(zp[c], eps2) + stage_recon_minus<T, ORDER>(zm[c], eps2);
+        }
     };
 
     // fill: planes k0 - R .. k0 + R - 1 (the z window of face k0 - 1/2)
@@ -329,8 +402,7 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
     }
     T Fl[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
-        Fl[c] = stage_recon_plus<T, ORDER>(zp[c], eps2) + stage_recon_minus<T, ORDER>(zm[c], eps2);
+    for (int c = 0; c < 5; ++c) Fl[c] = doz ? zface(c) : (T)0;
 
     // main loop: plane m = k + R enters, cell k is finished
     for (int k = k0; k < kend; ++k) {
@@ -349,7 +421,7 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
         T Lk[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            const T Fr = stage_recon_plus<T, ORDER>(zp[c], eps2) + stage_recon_minus<T, ORDER>(zm[c], eps2);
+            const T Fr = doz ? zface(c) : (T)0;
             const T Lz = (Fl[c] - Fr) * hzinv;
             Fl[c] = Fr;
             Lk[c] = ring[0][c] + Lz;
@@ -380,8 +452,6 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX>::value)) st
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-bool stage_fused_applies(const int n[3]) { return n[0] > 1 && n[1] > 1 && n[2] > 1; }
-
 int stage_default_segment(const int n[3], int tx) {
     // enough blocks to fill the chip several times over (about 3 x 256 x 4
     // resident blocks), segments of 16 to 64 planes (each segment re-enters
@@ -410,32 +480,45 @@ void stage_shape(StageGrid<T>& g, int tx, int seg) {
 }
 
 template <class T, int ORDER, int TX>
-static void launch_stage_t(bool hub, const StageArgs<T>& a, dim3 grid, hipStream_t s) {
-    if (hub) stage_fused<T, ORDER, TX, true><<<grid, 256, 0, s>>>(a);
-    else stage_fused<T, ORDER, TX, false><<<grid, 256, 0, s>>>(a);
+static hipError_t launch_stage_t(bool hub, bool local, int eos, const StageArgs<T>& a, dim3 grid, hipStream_t s) {
+    if (eos == EOS_CONFORMAL) {
+        if (hub && local) stage_fused<T, ORDER, TX, true, true, EOS_CONFORMAL><<<grid, 256, 0, s>>>(a);
+        else if (hub) stage_fused<T, ORDER, TX, true, false, EOS_CONFORMAL><<<grid, 256, 0, s>>>(a);
+        else if (local) stage_fused<T, ORDER, TX, false, true, EOS_CONFORMAL><<<grid, 256, 0, s>>>(a);
+        else stage_fused<T, ORDER, TX, false, false, EOS_CONFORMAL><<<grid, 256, 0, s>>>(a);
+    } else if (eos == EOS_IDEAL && !hub) {
+        // analytic boundaries are the conformal fluid's
+        if (local) stage_fused<T, ORDER, TX, false, true, EOS_IDEAL><<<grid, 256, 0, s>>>(a);
+        else stage_fused<T, ORDER, TX, false, false, EOS_IDEAL><<<grid, 256, 0, s>>>(a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipSuccess;
 }
 
 template <class T>
-hipError_t launch_stage(int order, int tx, bool hub, const StageArgs<T>& a, long long nblocks, hipStream_t s) {
+hipError_t launch_stage(int order, int tx, bool hub, bool local, int eos, const StageArgs<T>& a,
+                        long long nblocks, hipStream_t s) {
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nblocks);
+    hipError_t e;
     if (order == 5) {
-        if (tx == 16) launch_stage_t<T, 5, 16>(hub, a, grid, s);
-        else if (tx == 32) launch_stage_t<T, 5, 32>(hub, a, grid, s);
+        if (tx == 16) e = launch_stage_t<T, 5, 16>(hub, local, eos, a, grid, s);
+        else if (tx == 32) e = launch_stage_t<T, 5, 32>(hub, local, eos, a, grid, s);
         else return hipErrorInvalidValue;
     } else if (order == 7) {
         // WENO7 tiles are 16 x 16 (a 32 x 8 tile has 320 halo cells per plane)
-        if (tx == 16) launch_stage_t<T, 7, 16>(hub, a, grid, s);
+        if (tx == 16) e = launch_stage_t<T, 7, 16>(hub, local, eos, a, grid, s);
         else return hipErrorInvalidValue;
     } else {
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 template void stage_shape<float>(StageGrid<float>&, int, int);
 template void stage_shape<double>(StageGrid<double>&, int, int);
-template hipError_t launch_stage<float>(int, int, bool, const StageArgs<float>&, long long, hipStream_t);
-template hipError_t launch_stage<double>(int, int, bool, const StageArgs<double>&, long long, hipStream_t);
+template hipError_t launch_stage<float>(int, int, bool, bool, int, const StageArgs<float>&, long long, hipStream_t);
+template hipError_t launch_stage<double>(int, int, bool, bool, int, const StageArgs<double>&, long long, hipStream_t);
 
 }  // namespace rh

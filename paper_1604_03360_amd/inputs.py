@@ -179,3 +179,41 @@ def random_smooth(shape, h=0.1, seed=0, amp_v=0.3, bc=(BC_PERIODIC,) * 3, order=
     prim[4] = 0.5 + 0.25 * np.tanh(field())
     c0 = tuple(-(0.5 * s - 0.5) * h for s in shape)
     return _spec("random_smooth", shape, (h, h, h), c0, bc, prim, order=order)
+
+
+def with_scheme(spec, **opts):
+    """A copy of a workload spec with scheme options attached: order (5, 7, or 2 for
+    MUSTA-FORCE), limiter, musta_k, musta_cfl, lf_local, eos, gamma."""
+    out = dict(spec)
+    out.update(opts)
+    return out
+
+
+def hot_gas(spec):
+    """A copy of a workload spec whose energy density is raised by twice the charge
+    density (e -> e + 2n), so that an ideal gas of unit rest mass per charge has
+    positive pressure everywhere."""
+    out = dict(spec)
+    prim = spec["prim"].copy()
+    prim[0] = prim[0] + 2.0 * prim[4]
+    out["prim"] = prim
+    return out
+
+
+def sod_ideal(nx=400, nsteps=None):
+    """Relativistic shock tube of an ideal gas (gamma = 5/3) on x in [-1, 1], at rest:
+    x < 0: e = 29.995, n = 10; x > 0: e = 1.0000015, n = 1 (pressures 13.33 and 1e-6
+    for gamma = 5/3, the first relativistic shock tube of Marti and Mueller).
+    Outflow boundaries; t = 0.4 after the default number of steps."""
+    h = 2.0 / nx
+    x = _centres(nx, h, -1.0 + 0.5 * h)
+    prim = np.zeros((5, 1, 1, nx))
+    left = x < 0.0
+    prim[0, 0, 0] = np.where(left, 29.995, 1.0000015)
+    prim[4, 0, 0] = np.where(left, 10.0, 1.0)
+    steps = nsteps if nsteps is not None else int(round(0.4 / (CFL * h)))
+    spec = _spec("sod_ideal", (nx, 1, 1), (h, h, h), (-1.0 + 0.5 * h, 0.0, 0.0),
+                 (BC_OUTFLOW,) * 3, prim, nsteps=steps)
+    spec["eos"] = 1
+    spec["gamma"] = 5.0 / 3.0
+    return spec

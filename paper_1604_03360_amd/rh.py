@@ -23,6 +23,10 @@ RH_KERNEL_STAGE = 6
 RH_KERNEL_CLASSES = 7
 KERNEL_NAMES = ("sweep_x", "sweep_y", "sweep_z", "other", "adjoint", "sweep_xy", "stage")
 RH_PATH_AUTO, RH_PATH_SWEEPS, RH_PATH_STAGE = 0, 1, 2
+RH_SCHEME_MUSTA = 2
+RH_LIMITER_MINMOD, RH_LIMITER_MC, RH_LIMITER_VANLEER, RH_LIMITER_SUPERBEE, RH_LIMITER_NONE = 0, 1, 2, 3, 4
+RH_SPLIT_GLOBAL, RH_SPLIT_LOCAL = 0, 1
+RH_EOS_CONFORMAL, RH_EOS_IDEAL = 0, 1
 RH_NOALLOC_MAX_BYTES = 4294967295
 
 
@@ -33,7 +37,9 @@ class rh_grid_desc(ctypes.Structure):
                 ("scheme", ctypes.c_int), ("precision", ctypes.c_int), ("bc", ctypes.c_int * 3),
                 ("weno_eps", ctypes.c_double), ("hubble_t0", ctypes.c_double),
                 ("hubble_e0", ctypes.c_double), ("hubble_n0", ctypes.c_double),
-                ("strict", ctypes.c_int)]
+                ("strict", ctypes.c_int), ("limiter", ctypes.c_int), ("musta_stages", ctypes.c_int),
+                ("musta_cfl", ctypes.c_double), ("flux_split", ctypes.c_int), ("eos", ctypes.c_int),
+                ("eos_gamma", ctypes.c_double)]
 
 
 class RHError(RuntimeError):
@@ -228,8 +234,15 @@ def rh_step_vjp_stored(plan, t, dt, un_ptr, stages_ptr, bin_ptr, bout_ptr, scrat
 
 
 def make_desc(shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC,) * 3,
-              eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False):
+              eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False, limiter=RH_LIMITER_MINMOD, musta_stages=0,
+              musta_cfl=0.0, flux_split=RH_SPLIT_GLOBAL, eos=RH_EOS_CONFORMAL, eos_gamma=0.0):
     d = rh_grid_desc()
+    d.limiter = int(limiter)
+    d.musta_stages = int(musta_stages)
+    d.musta_cfl = float(musta_cfl)
+    d.flux_split = int(flux_split)
+    d.eos = int(eos)
+    d.eos_gamma = float(eos_gamma)
     d.nx, d.ny, d.nz = (int(s) for s in shape)
     d.dx, d.dy, d.dz = (float(v) for v in h)
     d.x0, d.y0, d.z0 = (float(v) for v in c0)
@@ -243,16 +256,35 @@ def make_desc(shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC
     return d
 
 
+def scheme_options(spec):
+    """make_desc keywords of the scheme options a workload spec carries (MUSTA-FORCE
+    limiter, stage count and local Courant number; local splitting; equation of state)."""
+    out = {}
+    if "limiter" in spec:
+        out["limiter"] = spec["limiter"]
+    if "musta_k" in spec:
+        out["musta_stages"] = spec["musta_k"]
+    if "musta_cfl" in spec:
+        out["musta_cfl"] = spec["musta_cfl"]
+    if spec.get("lf_local"):
+        out["flux_split"] = RH_SPLIT_LOCAL
+    if "eos" in spec:
+        out["eos"] = spec["eos"]
+    if "gamma" in spec:
+        out["eos_gamma"] = spec["gamma"]
+    return out
+
+
 class Hydro:
     """One grid on the GPU: torch owns the state and workspace tensors, the
     library does all the work on torch's current stream."""
 
     def __init__(self, shape, h, c0, scheme=5, precision=RH_PREC_FP64, bc=(RH_BC_PERIODIC,) * 3,
-                 eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False, device="cuda", t=0.0):
+                 eps=1e-6, hub=(10.0, 1.0, 0.5), strict=False, device="cuda", t=0.0, **scheme_opts):
         import torch
         self.torch = torch
         self.shape = tuple(int(s) for s in shape)
-        self.desc = make_desc(shape, h, c0, scheme, precision, bc, eps, hub, strict)
+        self.desc = make_desc(shape, h, c0, scheme, precision, bc, eps, hub, strict, **scheme_opts)
         self.plan = rh_plan_create(self.desc)
         self.dtype = torch.float32 if precision == RH_PREC_FP32 else torch.float64
         nx, ny, nz = self.shape
@@ -266,9 +298,11 @@ class Hydro:
 
     @classmethod
     def from_spec(cls, spec, precision=RH_PREC_FP64, scheme=None, **kw):
+        opts = scheme_options(spec)
+        opts.update(kw)
         return cls(spec["shape"], spec["h"], spec["c0"], scheme=scheme or spec["order"],
                    precision=precision, bc=spec["bc"], eps=spec.get("eps", 1e-6),
-                   hub=spec.get("hub", (10.0, 1.0, 0.5)), t=spec.get("t0", 0.0), **kw)
+                   hub=spec.get("hub", (10.0, 1.0, 0.5)), t=spec.get("t0", 0.0), **opts)
 
     def stream_ptr(self):
         return self.torch.cuda.current_stream(self.device).cuda_stream
@@ -495,7 +529,8 @@ class Batch:
         self.device = torch.device(device)
         self.specs = specs
         self.descs = [make_desc(sp["shape"], sp["h"], sp["c0"], scheme or sp["order"], precision,
-                                sp["bc"], sp.get("eps", 1e-6), sp.get("hub", (10.0, 1.0, 0.5)))
+                                sp["bc"], sp.get("eps", 1e-6), sp.get("hub", (10.0, 1.0, 0.5)),
+                                **scheme_options(sp))
                       for sp in specs]
         self.batch = rh_batch_create(self.descs)
         self.n = len(specs)

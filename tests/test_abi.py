@@ -40,17 +40,24 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layout_matches_header():
     from paper_1604_03360_amd import rh
-    # ints: nx ny nz | pad | 6 doubles | scheme precision bc[3] | pad | 4 doubles | strict | pad
-    assert ctypes.sizeof(rh.rh_grid_desc) == 4 * 3 + 4 + 8 * 6 + 4 * 5 + 4 + 8 * 4 + 8
+    # ints: nx ny nz | pad | 6 doubles | scheme precision bc[3] | pad | 4 doubles | strict limiter
+    # | musta_stages pad | musta_cfl | flux_split eos | eos_gamma
+    assert ctypes.sizeof(rh.rh_grid_desc) == 160
     assert rh.rh_grid_desc.dx.offset == 16
     assert rh.rh_grid_desc.scheme.offset == 64
     assert rh.rh_grid_desc.weno_eps.offset == 88
+    assert rh.rh_grid_desc.strict.offset == 120
+    assert rh.rh_grid_desc.limiter.offset == 124
+    assert rh.rh_grid_desc.musta_cfl.offset == 136
+    assert rh.rh_grid_desc.eos_gamma.offset == 152
 
 
 def test_invalid_descriptions_are_rejected_without_a_gpu(lib):
     from paper_1604_03360_amd import rh
     bad = [dict(scheme=6), dict(precision=3), dict(bc=(0, 0, 9)), dict(h=(0.1, -1.0, 0.1)),
-           dict(shape=(0, 4, 4))]
+           dict(shape=(0, 4, 4)), dict(scheme=2, limiter=9), dict(scheme=2, musta_stages=9),
+           dict(scheme=2, musta_cfl=1.5), dict(eos=5), dict(eos=1, eos_gamma=2.5), dict(flux_split=3),
+           dict(scheme=2, flux_split=1)]
     for kw in bad:
         args = dict(shape=(8, 8, 8), h=(0.1,) * 3, c0=(0, 0, 0))
         args.update(kw)
@@ -77,3 +84,11 @@ def test_noalloc_totals_rejects_bad_arguments_without_a_gpu(lib):
     for state, prec, ncell, out in cases:
         assert lib.rh_totals_noalloc(state, prec, ncell, out, None) == rh.RH_E_INVAL
         assert rh.rh_last_error()
+
+
+def test_hubble_boundaries_need_the_conformal_fluid(lib):
+    from paper_1604_03360_amd import rh
+    d = rh.make_desc((8, 8, 8), (0.1,) * 3, (0, 0, 0), bc=(rh.RH_BC_HUBBLE,) * 3, eos=rh.RH_EOS_IDEAL)
+    with pytest.raises(rh.RHError) as ei:
+        rh.rh_plan_create(d)
+    assert ei.value.status == rh.RH_E_NOTSUP
