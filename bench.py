@@ -13,6 +13,10 @@ Runge-Kutta in FP32, primitive recovery in FP64); the FP64 run is reported
 beside it.  The roofline block is for the dominant sweep kernel, timed live
 with HIP events on the library's stream; the CPU baseline is the FP64 oracle on
 the host cores over a bounded sample (whole-grid steps of the same workload).
+Side blocks: WENO7, the adjoint, the differentiable run, the 64-event ensemble,
+the other schemes (MUSTA-FORCE, local splitting, ideal gas) on the same blob,
+and the per-field error of the 128^3 Hubble-like flow after 100 steps against
+the FP64 oracle.
 """
 import argparse
 import hashlib
@@ -26,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "WENO5-RK3 cell-updates/s @256^3 FP32 vs FP64, %HBM peak; adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
+SETTLE_S = 0.3
 # MI355X vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s (packed), FP64 78.6 TFLOP/s
 ALU_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
@@ -38,6 +43,16 @@ WENO_FLOPS = {5: 69, 7: 194}
 
 def sweep_flops_per_cell(order):
     return 10 * WENO_FLOPS[order] + 5 + 25 + 10 + 20.0 / 3.0 + 5
+
+
+# MUSTA-FORCE (same counting rules), per face: MUSCL states 5 x (2 slopes of 6
+# operations + 2 half-slope updates of 2) = 80; per stage three physical fluxes,
+# each a recovery (about 20) and the flux (8), the Richtmyer state (5 x 4), the
+# FORCE flux (5 x 7) and, between stages, the corrector (5 x 4); per cell and axis
+# one face, the flux difference (10) and the accumulation of L (5).
+def musta_flops_per_cell_axis(k):
+    per_stage = 3 * (20 + 8) + 20 + 35
+    return 80 + k * per_stage + (k - 1) * 20 + 10 + 5
 
 
 # HBM values per cell that each sweep class must move in this split-sweep design:
@@ -80,19 +95,48 @@ def load_traffic(kernel, precision, order=5):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-# one VALU wave instruction per CU per cycle is the unpacked issue rate
+def load_trace_avg(kernel, precision, order=5):
+    """Average launch time (ms) of one kernel class at 256^3 in the committed
+    kernel trace of the default benchmark command, if taken on the current
+    kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "bench_default_kernel_trace.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    ent = rec.get("kernels", {}).get("%s|%s|%d" % (precision, kernel, order))
+    return None if ent is None else ent.get("avg_ms_settled")
+
+
+# one VALU wave instruction per CU per cycle is the nominal unpacked issue rate
 # (4 SIMDs, a wave64 instruction every 4 cycles each): 256 CUs x 2.4 GHz
 VALU_WAVE_ISSUE_PER_S = 256 * 2.4e9
 
 
-def run_gpu(spec, precision, steps, warmup):
+def run_gpu(spec, precision, steps, warmup, path=None):
     import torch
     from paper_1604_03360_amd import rh
     prec = rh.RH_PREC_FP32 if precision == "fp32" else rh.RH_PREC_FP64
     h = rh.Hydro.from_spec(spec, precision=prec)
+    if path is not None:
+        rh.rh_set_path(h.plan, path)
     h.set_primitive(spec["prim"])
     rh.rh_set_graph(h.plan, 1)   # steps replayed from one captured graph
     dt = spec["dt"]
+    # Untimed clock settling before the warm-up steps: the GPU raises its clock
+    # over the first few hundred milliseconds of sustained work (the same kernel
+    # ran 10-40% longer in the first 50 ms of a run than after 0.3 s), so steps
+    # are replayed until at least SETTLE_S seconds of them have run.
+    settle_steps = 0
+    s0 = time.perf_counter()
+    while time.perf_counter() - s0 < SETTLE_S:
+        h.step(dt, 4)
+        torch.cuda.synchronize()
+        settle_steps += 4
     if warmup:
         h.step(dt, warmup)
     stream = torch.cuda.current_stream()
@@ -120,7 +164,7 @@ def run_gpu(spec, precision, steps, warmup):
     torch.cuda.empty_cache()
     ncell = spec["shape"][0] * spec["shape"][1] * spec["shape"][2]
     return {"ms_per_step": ms_total / steps, "wall_s": wall, "value": ncell * steps / (ms_total * 1e-3),
-            "kernels": ktimes, "totals": tot, "counters": cnt}
+            "kernels": ktimes, "totals": tot, "counters": cnt, "settle_steps": settle_steps}
 
 
 def run_adjoint(spec, precision, reps, repeats=5):
@@ -258,6 +302,96 @@ def run_batch(steps, warmup):
                         "dx=0.15, dt=0.06, one batch"}
 
 
+def run_schemes(n, steps, warmup):
+    """The 256^3 blob with the other schemes of the library, each one fused launch
+    per stage: MUSTA-FORCE (minmod, two stages, the paper's other scheme) in FP32
+    and FP64, WENO5 with local Lax-Friedrichs splitting (FP32), and WENO5 with the
+    ideal gas (gamma 5/3, FP32; the blob heated so that e > n).  The fused WENO5
+    stage with global splitting is timed beside them for reference."""
+    from paper_1604_03360_amd import inputs, rh
+    base = inputs.blob(n=n, order=5)
+    ncell = n ** 3
+    legs = {
+        "musta_fp32": (inputs.with_scheme(base, order=2, limiter=0, musta_k=2), "fp32"),
+        "musta_fp64": (inputs.with_scheme(base, order=2, limiter=0, musta_k=2), "fp64"),
+        "weno5_stage_fp32": (base, "fp32"),
+        "weno5_local_split_fp32": (inputs.with_scheme(base, lf_local=True), "fp32"),
+        "weno5_ideal_gas_fp32": (inputs.with_scheme(inputs.hot_gas(base), eos=1, gamma=5.0 / 3.0), "fp32"),
+    }
+    out = {}
+    for name, (sp, prec) in legs.items():
+        r = run_gpu(sp, prec, steps, warmup, path=rh.RH_PATH_STAGE)
+        ms, launches = r["kernels"]["stage"]
+        ent = {"value": r["value"], "unit": "cell-updates/s", "ms_per_step": r["ms_per_step"],
+               "stage_launch_ms": ms / launches, "counters": r["counters"]}
+        if name.startswith("musta"):
+            flops = 3 * musta_flops_per_cell_axis(2) * ncell
+            achieved = flops / (ms / launches * 1e-3) / 1e12
+            ent["roofline"] = {"bound": "alu", "kernel": "stage_musta", "achieved": round(achieved, 3),
+                               "peak": ALU_PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                               "frac": round(achieved / ALU_PEAK_TFLOPS[prec], 4),
+                               "flops_per_cell_launch": 3 * musta_flops_per_cell_axis(2)}
+        out[name] = ent
+        print("bench: %s %.4g cell-updates/s (%.3f ms/step)" % (name, r["value"], r["ms_per_step"]),
+              file=sys.stderr, flush=True)
+    out["musta_over_weno5_time"] = out["weno5_stage_fp32"]["value"] / out["musta_fp32"]["value"]
+    out["workload"] = "%d^3 blob, %d steps each, fused stage; MUSTA-FORCE minmod, 2 stages, local dt/dx 0.9" % (n, steps)
+    return out
+
+
+def musta_cpu_sample(gpu_value):
+    """The paper's only speed figure compares its MUSTA-FORCE GPU program with a
+    single-threaded CPU one.  For context: the oracle's MUSTA-FORCE, one thread,
+    one step of the blob at 64^3, against the FP32 GPU figure of the leg above."""
+    import oracle
+    from paper_1604_03360_amd import inputs
+    sp = inputs.with_scheme(inputs.blob(n=64, order=5), order=2, limiter=0, musta_k=2)
+    g = oracle.grid_from_spec(sp)
+    u = oracle.prim2con(sp["prim"])
+    cores = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(g, u, sp["dt"], 1)
+        el = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    v = 64 ** 3 / el
+    return {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "1 MUSTA-FORCE SSP-RK3 step of the blob at 64^3 (dx 0.1), FP64, %.1f s" % el,
+            "gpu_fp32_over_this": gpu_value / v}
+
+
+def hubble_field_errors(n=128, nsteps=100):
+    """Per-field error of the 128^3 Hubble-like flow after its 100 steps: the FP32
+    and FP64 GPU states against the FP64 oracle (normalised L-infinity,
+    max|gpu - oracle| / max|oracle| per field), and the energy density of each
+    against the closed form on interior cells."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1604_03360_amd import inputs, rh
+    spec = inputs.hubble(n=n)
+    g = oracle.grid_from_spec(spec)
+    t0 = time.perf_counter()
+    ref, t_end = oracle.step(g, oracle.prim2con(spec["prim"]), spec["dt"], nsteps, t=spec["t0"])
+    cpu_s = time.perf_counter() - t0
+    names = ("E", "Mx", "My", "Mz", "N")
+    out = {"grid": [n] * 3, "steps": nsteps, "t_end": t_end, "oracle_s": round(cpu_s, 1),
+           "norm": "max|gpu - oracle| / max|oracle| per field"}
+    for prec, code in (("fp32", rh.RH_PREC_FP32), ("fp64", rh.RH_PREC_FP64)):
+        h = rh.Hydro.from_spec(spec, precision=code)
+        h.set_primitive(spec["prim"])
+        h.step(spec["dt"], nsteps)
+        got = h.get()
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+        d = np.abs(got - ref).reshape(5, -1).max(1) / np.abs(ref).reshape(5, -1).max(1)
+        out[prec] = {k: float(v) for k, v in zip(names, d)}
+    return out
+
+
 def roofline(run, precision, order, ncell):
     elem = 4 if precision == "fp32" else 8
     kern = {k: v for k, v in run["kernels"].items() if k.startswith("sweep") and v[1] > 0}
@@ -295,20 +429,32 @@ def roofline(run, precision, order, ncell):
         hbm["step_counted"] = {"bytes": counted, "GBps": round(counted / step_s / 1e9, 1),
                                "frac": round(counted / step_s / 1e9 / HBM_PEAK_GBS, 4)}
     valu = None
-    if dom in prof and "SQ_INSTS_VALU" in prof[dom]:
-        wi = prof[dom]["SQ_INSTS_VALU"]
-        rate = wi / avg_s / VALU_WAVE_ISSUE_PER_S
+    if dom in prof and "SQ_INSTS_VALU" in prof[dom] and prof[dom].get("_dur_valu_run"):
+        # counted VALU wave instructions over the duration of the same counter
+        # pass's dispatch (not this run's event time), per CU and clock cycle
+        ent = prof[dom]
+        wi, dur = ent["SQ_INSTS_VALU"], ent["_dur_valu_run"]
+        rate = wi / dur / VALU_WAVE_ISSUE_PER_S
         valu = {"kernel": dom, "wave_instr_per_launch": wi, "instr_per_cell": round(wi * 64 / ncell, 1),
-                "wave_instr_per_cu_cycle": round(rate, 4),
-                "frac_of_unpacked_issue": round(rate, 4),
-                # the FP32 peak counts packed dual FP32; FP64 issues at the unpacked rate
-                "frac_of_peak": round(rate / 2.0, 4) if precision == "fp32" else round(rate, 4)}
-    return dom, {
+                "time_base": "dispatch duration in the counter pass (%.1f us)" % (dur * 1e6),
+                "wave_instr_per_cu_cycle_at_2.4GHz": round(rate, 4)}
+        if ent.get("clock_ghz"):
+            valu["clock_ghz_measured"] = round(ent["clock_ghz"], 3)
+            valu["wave_instr_per_cu_cycle"] = round(wi / dur / (256 * ent["clock_ghz"] * 1e9), 4)
+        if ent.get("valu_busy") is not None:
+            valu["valu_busy"] = round(ent["valu_busy"], 4)
+    out = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4), "traffic": traffic,
         "kernel": dom, "avg_launch_ms": round(ms / launches, 4),
         "flops_per_cell": flops_cell, "valu": valu,
-    }, hbm
+    }
+    tr = load_trace_avg(dom, precision, order)
+    if tr:
+        # the same figure from the committed kernel trace of the default command
+        out["trace_avg_launch_ms"] = round(tr, 4)
+        out["frac_trace"] = round(flops / (tr * 1e-3) / 1e12 / peak, 4)
+    return dom, out, hbm
 
 
 def cpu_baseline(spec, nsteps):
@@ -372,6 +518,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-weno7", action="store_true")
+    ap.add_argument("--no-schemes", action="store_true")
+    ap.add_argument("--no-hubble", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (reference "
                          "for scaling hardware byte counters)")
@@ -449,7 +597,22 @@ def main():
               file=sys.stderr, flush=True)
         return b
 
+    def schemes_leg():
+        sc = run_schemes(args.n, min(args.steps, 10), min(args.warmup, 2))
+        if not args.no_cpu_baseline:
+            sc["musta_cpu_single_thread"] = side_leg("MUSTA CPU sample",
+                                                     lambda: musta_cpu_sample(sc["musta_fp32"]["value"]))
+        return sc
+
+    def hubble_leg():
+        hf = hubble_field_errors()
+        print("bench: Hubble 128^3 after 100 steps, FP32 per-field error vs the FP64 oracle %s"
+              % hf["fp32"], file=sys.stderr, flush=True)
+        return hf
+
     w7 = side_leg("WENO7", weno7_leg) if args.scheme == 5 and not args.no_weno7 else None
+    sch = side_leg("schemes", schemes_leg) if not args.no_schemes else None
+    hub = side_leg("Hubble per-field errors", hubble_leg) if not args.no_hubble else None
     adj = side_leg("adjoint", adjoint_leg) if not args.no_adjoint else None
     diff = side_leg("differentiable run", diff_leg) if not args.no_adjoint else None
     bat = side_leg("batch", batch_leg) if not args.no_batch else None
@@ -478,6 +641,10 @@ def main():
         out["differentiable_run"] = diff
     if bat is not None:
         out["batch"] = bat
+    if sch is not None:
+        out["schemes"] = sch
+    if hub is not None:
+        out["fp32_error_per_field"] = hub
     if r64 is not None:
         _, roof64, hbm64 = roofline(r64, "fp64", args.scheme, ncell)
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],

@@ -183,8 +183,11 @@ __device__ __forceinline__ double ideal_p(double gm1, double e, double n) {
 //   g(v) = v (E + p(E - |M| v, N sqrt(1 - v^2))) - |M| = 0,
 // g increasing on [0, 1) (dg/dv >= E - (gamma - 1)|M| > 0 for gamma <= 2), with
 // the root inside [|M| / (gamma E), |M| / E] because 0 <= p <= (gamma - 1) E.
-// Newton steps from the upper end, kept inside the shrinking bracket (a step
-// leaving it is replaced by bisection), stop at a relative change of 1e-15.
+// Newton steps, kept inside the shrinking bracket (a step leaving it is
+// replaced by bisection), stop at a relative change of 1e-15.  They start from
+// the root for the same fluid without rest mass (n = 0, p = (gamma - 1) e), the
+// smaller root of (gamma - 1)|M| v^2 - gamma E v + |M| = 0, which lies in the
+// bracket and is exact when N = 0.
 // Floors as the closed form: E below the floor -> at rest; |M|^2 capped.
 __device__ inline void recover_ideal(double E, double Mx, double My, double Mz, double N, double gm1,
                                      double& kap, double& Mxs, double& Mys, double& Mzs, double& p,
@@ -217,15 +220,21 @@ __device__ inline void recover_ideal(double E, double Mx, double My, double Mz, 
         return;
     }
     const double M = sqrt(M2);
-    double lo = M / ((gm1 + 1.0) * E), hi = M / E, v = hi;
+    const double ge = (gm1 + 1.0) * E;
+    double lo = M / ge, hi = M / E;
+    // 2|M| / (gamma E + sqrt(gamma^2 E^2 - 4 (gamma - 1) M^2)); the radicand is at
+    // least (2 - gamma)^2 E^2 >= 0
+    const double rad = ge * ge - 4.0 * gm1 * M2;
+    double v = 2.0 * M / (ge + sqrt(rad > 0.0 ? rad : 0.0));
+    v = v < lo ? lo : (v > hi ? hi : v);
 #pragma unroll 1
     for (int it = 0; it < 80; ++it) {
-        const double w = sqrt(1.0 - v * v);
+        const double w = sqrt_pos(1.0 - v * v);
         const double pr = gm1 * ((E - M * v) - N * w);
         double g, dg;
         if (pr > 0.0) {
             g = v * (E + pr) - M;
-            dg = (E + pr) + v * gm1 * (N * v / w - M);
+            dg = (E + pr) + v * gm1 * (N * v * fast_rcp(w) - M);
         } else {
             g = v * E - M;
             dg = E;
@@ -233,7 +242,7 @@ __device__ inline void recover_ideal(double E, double Mx, double My, double Mz, 
         if (g == 0.0) break;
         if (g > 0.0) hi = v;
         else lo = v;
-        double vn = v - g / dg;
+        double vn = v - g * fast_rcp(dg);
         if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
         const double dv = fabs(vn - v);
         v = vn;

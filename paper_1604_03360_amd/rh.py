@@ -468,6 +468,42 @@ def rh_batch_autotune(batch, reps=3):
     return rh_batch_get_tuning(batch)
 
 
+def autotune_key(descs, path, device=""):
+    """Text key of a tuned launch shape (independent of the order of the grids)."""
+    sizes = {}
+    for d in descs:
+        k = "%dx%dx%d" % (d.nx, d.ny, d.nz)
+        sizes[k] = sizes.get(k, 0) + 1
+    d0 = descs[0]
+    return "|".join([device, "path=%d" % path, "scheme=%d" % d0.scheme, "precision=%d" % d0.precision,
+                     "eos=%d" % d0.eos, "split=%d" % d0.flux_split,
+                     "sizes=" + ",".join("%s*%d" % (k, sizes[k]) for k in sorted(sizes))])
+
+
+def load_autotune_cache(path):
+    import json
+    import os
+    if not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except ValueError:
+        return {}
+    return data if isinstance(data, dict) else {}
+
+
+def store_autotune_cache(path, key, shape):
+    import json
+    import os
+    data = load_autotune_cache(path)
+    data[key] = list(shape)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def rh_batch_set_path(batch, path):
     _check(library().rh_batch_set_path(batch, int(path)))
 
@@ -572,6 +608,34 @@ class Batch:
 
     def totals(self):
         return rh_batch_totals(self.batch, self.n)
+
+    def tuning_key(self):
+        """Key of this ensemble's launch-shape tuning: the evaluation path, scheme,
+        precision, equation of state, splitting and the multiset of grid sizes."""
+        return autotune_key(self.descs, rh_batch_get_path(self.batch), self.device_name())
+
+    def device_name(self):
+        return self.torch.cuda.get_device_name(self.device)
+
+    def autotune(self, reps=2, cache=None):
+        """Pick the launch shape of the batch's path: from the JSON file `cache`
+        when it holds an entry for this ensemble's key, else by timing the
+        candidates (rh_batch_autotune) and storing the result there.  Returns
+        (shape, "cache" or "timed")."""
+        key = self.tuning_key()
+        path = rh_batch_get_path(self.batch)
+        if cache is not None:
+            entry = load_autotune_cache(cache).get(key)
+            if entry is not None:
+                if path == RH_PATH_STAGE:
+                    rh_batch_set_stage_tuning(self.batch, *entry)
+                else:
+                    rh_batch_set_tuning(self.batch, *entry)
+                return tuple(entry), "cache"
+        shape = tuple(rh_batch_autotune(self.batch, reps))
+        if cache is not None:
+            store_autotune_cache(cache, key, shape)
+        return shape, "timed"
 
     def close(self):
         if self.batch is not None:

@@ -20,6 +20,7 @@ def fake_run(ms_per_step=2.0, launches=60):
 
 def test_roofline_arithmetic_without_profile(monkeypatch):
     monkeypatch.setattr(bench, "load_profile", lambda precision, order=5: {})
+    monkeypatch.setattr(bench, "load_trace_avg", lambda kernel, precision, order=5: None)
     n = 256 ** 3
     dom, roof, hbm = bench.roofline(fake_run(), "fp32", 5, n)
     assert dom == "sweep_z" and roof["kernel"] == "sweep_z"
@@ -28,6 +29,7 @@ def test_roofline_arithmetic_without_profile(monkeypatch):
     assert roof["achieved"] == pytest.approx(flops / avg_s / 1e12, rel=1e-3)
     assert roof["frac"] == pytest.approx(roof["achieved"] / 157.3, rel=1e-3)
     assert roof["bound"] == "alu" and roof["traffic"] is None and roof["valu"] is None
+    assert "frac_trace" not in roof
     # algorithmic bytes of the z sweep: (15 + 20 + 20) / 3 values of 4 B per cell
     assert hbm["design_bytes_per_launch"] == pytest.approx(55.0 / 3.0 * 4 * n)
     # whole step: 40 values per cell-update
@@ -37,19 +39,27 @@ def test_roofline_arithmetic_without_profile(monkeypatch):
 
 
 def test_roofline_uses_profile_counters(monkeypatch):
-    prof = {k: {"bytes_per_launch": b, "SQ_INSTS_VALU": 1.0e8}
+    # the counter pass's own dispatch duration (2.6e-4 s) is the time base of the
+    # issue rate, not the live event time (2.5e-4 s per launch)
+    prof = {k: {"bytes_per_launch": b, "SQ_INSTS_VALU": 1.0e8, "_dur_valu_run": 2.6e-4,
+                "clock_ghz": 2.2, "valu_busy": 0.93}
             for k, b in (("sweep_x", 1.0e9), ("sweep_y", 1.1e9), ("sweep_z", 1.3e9))}
     monkeypatch.setattr(bench, "load_profile", lambda precision, order=5: prof)
+    monkeypatch.setattr(bench, "load_trace_avg", lambda kernel, precision, order=5: 0.255)
     n = 256 ** 3
     _, roof, hbm = bench.roofline(fake_run(), "fp32", 5, n)
     avg_s = 15.0 / 60 * 1e-3
     assert roof["traffic"] == 1.3e9
     assert hbm["counted_GBps"] == pytest.approx(1.3e9 / avg_s / 1e9, rel=1e-3)
     assert hbm["step_counted"]["bytes"] == pytest.approx(3 * 3.4e9)
-    rate = 1.0e8 / avg_s / (256 * 2.4e9)
-    assert roof["valu"]["wave_instr_per_cu_cycle"] == pytest.approx(rate, rel=1e-3)
-    assert roof["valu"]["frac_of_peak"] == pytest.approx(rate / 2, rel=1e-3)
+    assert roof["valu"]["wave_instr_per_cu_cycle_at_2.4GHz"] == pytest.approx(1.0e8 / 2.6e-4 / (256 * 2.4e9),
+                                                                             rel=1e-3)
+    assert roof["valu"]["wave_instr_per_cu_cycle"] == pytest.approx(1.0e8 / 2.6e-4 / (256 * 2.2e9), rel=1e-3)
+    assert roof["valu"]["valu_busy"] == 0.93
     assert roof["valu"]["instr_per_cell"] == pytest.approx(1.0e8 * 64 / n, rel=1e-3)
+    # the trace-based fraction uses the committed trace's average launch time
+    flops = bench.sweep_flops_per_cell(5) * n
+    assert roof["frac_trace"] == pytest.approx(flops / 0.255e-3 / 1e12 / 157.3, rel=1e-3)
 
 
 def test_profile_gated_on_hash_and_scheme(tmp_path, monkeypatch):
@@ -69,6 +79,7 @@ def test_profile_gated_on_hash_and_scheme(tmp_path, monkeypatch):
 
 def test_roofline_of_the_fused_sweep(monkeypatch):
     monkeypatch.setattr(bench, "load_profile", lambda precision, order=5: {})
+    monkeypatch.setattr(bench, "load_trace_avg", lambda kernel, precision, order=5: None)
     n = 256 ** 3
     run = {"kernels": {"sweep_x": (0.0, 0), "sweep_y": (0.0, 0), "sweep_xy": (18.0, 60),
                        "sweep_z": (15.0, 60)}, "ms_per_step": 2.0}
@@ -86,3 +97,24 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The tuned launch shape of an ensemble is stored under a key of its path,
+    scheme, precision and size multiset, independent of the order of the grids."""
+    from paper_1604_03360_amd import rh
+    a = rh.make_desc((64, 64, 64), (0.1,) * 3, (0, 0, 0), 5, rh.RH_PREC_FP32)
+    b = rh.make_desc((96, 96, 96), (0.1,) * 3, (0, 0, 0), 5, rh.RH_PREC_FP32)
+    k1 = rh.autotune_key([a, b, a], rh.RH_PATH_STAGE, "dev")
+    k2 = rh.autotune_key([b, a, a], rh.RH_PATH_STAGE, "dev")
+    assert k1 == k2 and "64x64x64*2" in k1 and "96x96x96*1" in k1
+    assert k1 != rh.autotune_key([a, b, a], rh.RH_PATH_SWEEPS, "dev")
+    assert k1 != rh.autotune_key([a, b], rh.RH_PATH_STAGE, "dev")
+    c = rh.make_desc((64, 64, 64), (0.1,) * 3, (0, 0, 0), 5, rh.RH_PREC_FP64)
+    assert k1 != rh.autotune_key([c, b, c], rh.RH_PATH_STAGE, "dev")
+    path = str(tmp_path / "tune.json")
+    assert rh.load_autotune_cache(path) == {}
+    rh.store_autotune_cache(path, k1, (16, 32))
+    rh.store_autotune_cache(path, "other", (32, 24))
+    assert rh.load_autotune_cache(path)[k1] == [16, 32]
+    assert rh.load_autotune_cache(path)["other"] == [32, 24]

@@ -210,3 +210,25 @@ def test_batch_grids_keep_their_own_eps_and_boundary_parameters(precision):
         for sp, u in zip(specs, got):
             ref = run_single(rh, sp, prec, 3, dt)
             assert np.array_equal(u, ref), (sp["name"], sp["eps"], sp["hub"])
+
+
+def test_autotune_cache_reused(tmp_path):
+    """A tuned shape stored in the JSON cache is applied to a second batch of the
+    same ensemble without timing, and gives the same bits."""
+    rh = rh_module()
+    specs = small_events(5, sizes=(24, 40, 32, 20))
+    dt = specs[0]["dt"]
+    cache = str(tmp_path / "tune.json")
+    out = []
+    for expect in ("timed", "cache"):
+        b = rh.Batch(specs, precision=rh.RH_PREC_FP32)
+        b.set_primitive([sp["prim"] for sp in specs])
+        shape, source = b.autotune(2, cache=cache)
+        assert source == expect
+        assert tuple(rh.rh_batch_get_stage_tuning(b.batch)) == tuple(shape)
+        b.step(dt, 2)
+        out.append((shape, b.get()))
+        b.close()
+    assert out[0][0] == out[1][0]
+    for a, c in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, c)
