@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     }
     T Fl[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Fl[c] = doz ? zface(c) : (T)0;
+    for (int c = 0; c < 5; ++c) Fl[c] = zface(c);
 
     // main loop: plane m = k + R enters, cell k is finished
     for (int k = k0; k < kend; ++k) {
@@ -421,8 +421,10 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
         T Lk[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            const T Fr = doz ? zface(c) : (T)0;
-            const T Lz = (Fl[c] - Fr) * hzinv;
+            // the z face is reconstructed for every grid (on ghost copies where nz is
+            // 1) and discarded by a select, which keeps it out of a branch
+            const T Fr = zface(c);
+            const T Lz = doz ? (Fl[c] - Fr) * hzinv : (T)0;
             Fl[c] = Fr;
             Lk[c] = ring[0][c] + Lz;
         }
