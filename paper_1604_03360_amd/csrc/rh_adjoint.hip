@@ -215,6 +215,12 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
     const int own_hi = (!periodic && k1 == nd && A.bc == RH_BC_OUTFLOW) ? (1 << 30) : k1;
     const T eps = A.eps;
     const T half = (T)0.5;
+    // adjoint fields this group changes: its own components, and with any
+    // momentum or charge component the energy and the momenta (through the
+    // velocity and pressure); the others are neither loaded nor stored
+    auto touched = [](int f) {
+        return (f >= CLO && f < CHI) || (CHI > 1 && f < 4) || (CLO == 0 && f == 1 + DIR);
+    };
 
     // doubled split fluxes F +- u of the group's components from a cell state:
     // the reconstruction is homogeneous of degree one in (f, sqrt(eps)), so its
@@ -258,7 +264,8 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
         }
         if (tgt == last_tgt) return;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) ubo[f] = ld_off(C.ub[f], off);
+        for (int f = 0; f < 5; ++f)
+            if (touched(f)) ubo[f] = ld_off(C.ub[f], off);
     };
     // ub += scale * sum over the group of (d f+_c/du)^T a+_c + (d f-_c/du)^T a-_c
     auto finish = [&](int tgt, const T apj[NC], const T amj[NC]) {
@@ -290,6 +297,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs<T>& A, const Column<T, DI
         const uint32_t off = C.cb + (uint32_t)tgt * C.sb;
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
+            if (!touched(f)) continue;
             ubo[f] = ubo[f] + A.scale * g[f];
             st_off(C.ub[f], off, ubo[f]);
         }
