@@ -324,6 +324,9 @@ def run_schemes(n, steps, warmup):
         ms, launches = r["kernels"]["stage"]
         ent = {"value": r["value"], "unit": "cell-updates/s", "ms_per_step": r["ms_per_step"],
                "stage_launch_ms": ms / launches, "counters": r["counters"]}
+        oms, olaunches = r["kernels"]["other"]
+        if "ideal" in name and olaunches > 0:
+            ent["recovery_launch_ms"] = oms / olaunches   # the per-cell Newton pass before each stage
         if name.startswith("musta"):
             flops = 3 * musta_flops_per_cell_axis(2) * ncell
             achieved = flops / (ms / launches * 1e-3) / 1e12

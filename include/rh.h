@@ -117,7 +117,8 @@ typedef int rh_status;
 /* Equations of state.  CONFORMAL: p = e/3 (closed-form primitive recovery).
  * IDEAL: ideal gas with unit rest mass per unit charge, p = (gamma - 1)(e - n),
  * never below 0, c_s^2 = gamma p / (e + p); primitive recovery by a bracketed
- * FP64 Newton iteration for the speed.  HUBBLE boundaries need CONFORMAL. */
+ * FP64 Newton iteration for the speed, once per cell and evaluation of L (a
+ * pass before the WENO stage).  HUBBLE boundaries need CONFORMAL. */
 #define RH_EOS_CONFORMAL 0
 #define RH_EOS_IDEAL     1
 
@@ -170,7 +171,9 @@ size_t rh_state_bytes(const rh_plan* plan);
 
 /* Bytes of the workspace the caller must provide to rh_bind: the two
  * intermediate Runge-Kutta stage states and the L accumulator (3 states).  The
- * adjoint calls use it as scratch (a six-field recovery pack). */
+ * adjoint calls use it as scratch (a six-field recovery pack); the ideal gas's
+ * WENO stage keeps each cell's recovered (vx, vy, vz, p, c_s^2) in the slot of
+ * the accumulator, which the fused stage does not otherwise use. */
 size_t rh_workspace_bytes(const rh_plan* plan);
 
 /* Bind caller-owned device buffers and a stream.  state: rh_state_bytes bytes,

@@ -217,6 +217,10 @@ hipError_t launch_stage_of(const rh_grid_desc& d, int tx, bool hub, const rh::St
     return rh::launch_stage<T>(d.scheme, tx, hub, d.flux_split == RH_SPLIT_LOCAL, d.eos, sa, nblocks, s);
 }
 
+// The ideal-gas WENO stage reads every cell's velocity, pressure and sound
+// speed from a recovery pass run before it (MUSTA-FORCE recovers its own).
+bool needs_recovery(const rh_grid_desc& d) { return d.eos == RH_EOS_IDEAL && d.scheme != RH_SCHEME_MUSTA; }
+
 // Path of a single grid's evaluations: the fused stage where it is requested
 // or where only it implements the scheme; RH_PATH_AUTO keeps the directional
 // sweeps otherwise.
@@ -265,6 +269,14 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
                                             : (musta ? rh::musta_default_segment(n)
                                                      : rh::stage_default_segment(n, p->stage_tx)));
         const long long nb = rh::stage_blocks(sa.one);
+        if (needs_recovery(p->d)) {
+            // the workspace's L slot is free on this path (the stage writes uout or lacc)
+            sa.prim = (T*)p->ws + 10 * (size_t)p->ncell;
+            rh_status st = timed_launch(p, RH_KERNEL_OTHER, [&] {
+                return rh::launch_recover_ideal<T>(sa, rh::recover_blocks(sa.one), p->stream);
+            }, "recovery launch");
+            if (st != RH_OK) return st;
+        }
         return timed_launch(p, RH_KERNEL_STAGE, [&] {
             return launch_stage_of<T>(p->d, p->stage_tx, any_hubble(p), sa, nb, p->stream);
         }, "stage launch");
@@ -685,6 +697,7 @@ struct rh_batch {
     void* d_grids = nullptr;         // BatchGrid<T>[ngrid]
     int stage_tx = 16, stage_seg = 32;       // fused stage
     long long stage_nblocks = 0;
+    long long recover_nblocks = 0;   // ideal-gas recovery pass over every grid
     void* d_stage = nullptr;         // StageGrid<T>[ngrid]
     // binding
     void* state = nullptr;
@@ -760,14 +773,18 @@ rh_status upload_batch_table(rh_batch* b) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     // fused-stage table: grids in order, each a contiguous range of logical blocks
     std::vector<rh::StageGrid<T>> sg(b->ngrid);
-    long long sacc = 0;
+    long long sacc = 0, racc = 0;
     for (int i = 0; i < b->ngrid; ++i) {
         fill_stage_grid<T>(sg[i], b->d[i], b->off[i], b->stage_tx, b->stage_seg);
         sg[i].blk0 = (int)sacc;
+        sg[i].rblk0 = (int)racc;
         sacc += rh::stage_blocks(sg[i]);
-        if (sacc > 0x7fffffffLL) return fail(RH_E_NOTSUP, "batch too large for one fused-stage launch");
+        racc += rh::recover_blocks(sg[i]);
+        if (sacc > 0x7fffffffLL || racc > 0x7fffffffLL)
+            return fail(RH_E_NOTSUP, "batch too large for one fused-stage launch");
     }
     b->stage_nblocks = sacc;
+    b->recover_nblocks = racc;
     if (!b->d_stage) {
         e = hipMalloc(&b->d_stage, sg.size() * sizeof(rh::StageGrid<T>));
         if (e != hipSuccess) return hip_fail(e, "hipMalloc");
@@ -811,7 +828,7 @@ rh_status batch_timed(rh_batch* b, hipStream_t s, int cls, F&& launch, const cha
 // fusing the stage combine (stage > 0) or storing L (stage == 0).
 template <class T>
 rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T* lacc, T* uout,
-                         double t, double dt, int stage) {
+                         double t, double dt, int stage, T* prim) {
     if (b->path != RH_PATH_SWEEPS) {
         // one launch: L along x, y and z of every grid and the stage combine
         rh::StageArgs<T> sa;
@@ -825,6 +842,13 @@ rh_status batch_evaluate(rh_batch* b, hipStream_t s, const T* us, const T* u0, T
         sa.clamps = b->d_clamps;
         sa.grids = (const rh::StageGrid<T>*)b->d_stage;
         sa.ngrid = b->ngrid;
+        if (needs_recovery(b->d[0])) {
+            sa.prim = prim;
+            rh_status st = batch_timed(b, s, RH_KERNEL_OTHER, [&] {
+                return rh::launch_recover_ideal<T>(sa, b->recover_nblocks, s);
+            }, "batched recovery launch");
+            if (st != RH_OK) return st;
+        }
         return batch_timed(b, s, RH_KERNEL_STAGE, [&] {
             return launch_stage_of<T>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, s);
         }, "batched stage launch");
@@ -859,9 +883,10 @@ rh_status batch_one_step(rh_batch* b, hipStream_t s, double t, double dt) {
     T* U1 = (T*)b->ws;
     T* U2 = U1 + S;
     T* Lc = U2 + S;
-    rh_status st = batch_evaluate<T>(b, s, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
-    if (st == RH_OK) st = batch_evaluate<T>(b, s, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2);
-    if (st == RH_OK) st = batch_evaluate<T>(b, s, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3);
+    // the stage path leaves Lc unused: the ideal gas's recovered fields go there
+    rh_status st = batch_evaluate<T>(b, s, U0, U0, Lc, U1, t, dt, rh::STAGE_1, Lc);
+    if (st == RH_OK) st = batch_evaluate<T>(b, s, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2, Lc);
+    if (st == RH_OK) st = batch_evaluate<T>(b, s, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3, Lc);
     return st;
 }
 
@@ -1228,9 +1253,10 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
     };
     if (b->path != RH_PATH_SWEEPS) {
         // fused stage: x-y tile width and z segment, timed on evaluations of L
-        // into the workspace's last state
+        // into the workspace's last state (the ideal gas's recovered fields, in
+        // the first, computed once before the timed launches)
         auto time_stage = [&](float* ms) -> rh_status {
-            auto one = [&]() -> rh_status {
+            auto one = [&](bool recover) -> rh_status {
                 hipError_t er;
                 if (b->precision == RH_PREC_FP32) {
                     rh::StageArgs<float> sa;
@@ -1238,30 +1264,35 @@ rh_status rh_batch_autotune(rh_batch* b, int reps) {
                     sa.us = (const float*)b->state;
                     sa.u0 = (const float*)b->state;
                     sa.out = (float*)b->ws + 2 * S;
+                    sa.prim = (float*)b->ws;
                     sa.stage = rh::STAGE_WRITE_L;
                     sa.clamps = b->d_clamps;
                     sa.grids = (const rh::StageGrid<float>*)b->d_stage;
                     sa.ngrid = b->ngrid;
-                    er = launch_stage_of<float>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
+                    if (recover) er = rh::launch_recover_ideal<float>(sa, b->recover_nblocks, b->stream);
+                    else er = launch_stage_of<float>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
                 } else {
                     rh::StageArgs<double> sa;
                     std::memset(&sa, 0, sizeof(sa));
                     sa.us = (const double*)b->state;
                     sa.u0 = (const double*)b->state;
                     sa.out = (double*)b->ws + 2 * S;
+                    sa.prim = (double*)b->ws;
                     sa.stage = rh::STAGE_WRITE_L;
                     sa.clamps = b->d_clamps;
                     sa.grids = (const rh::StageGrid<double>*)b->d_stage;
                     sa.ngrid = b->ngrid;
-                    er = launch_stage_of<double>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
+                    if (recover) er = rh::launch_recover_ideal<double>(sa, b->recover_nblocks, b->stream);
+                    else er = launch_stage_of<double>(b->d[0], b->stage_tx, b->any_hubble, sa, b->stage_nblocks, b->stream);
                 }
                 return er == hipSuccess ? RH_OK : hip_fail(er, "autotune launch");
             };
-            rh_status s2 = one();   // warm-up
+            rh_status s2 = needs_recovery(b->d[0]) ? one(true) : RH_OK;
+            if (s2 == RH_OK) s2 = one(false);   // warm-up
             if (s2 != RH_OK) return s2;
             if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
             for (int r = 0; r < reps; ++r)
-                if ((s2 = one()) != RH_OK) return s2;
+                if ((s2 = one(false)) != RH_OK) return s2;
             if ((e = hipEventRecord(e1, b->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
             if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
             if ((e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");

@@ -184,7 +184,7 @@ __device__ __forceinline__ double ideal_p(double gm1, double e, double n) {
 // g increasing on [0, 1) (dg/dv >= E - (gamma - 1)|M| > 0 for gamma <= 2), with
 // the root inside [|M| / (gamma E), |M| / E] because 0 <= p <= (gamma - 1) E.
 // Newton steps, kept inside the shrinking bracket (a step leaving it is
-// replaced by bisection), stop at a relative change of 1e-15.  They start from
+// replaced by bisection), stop at a relative step of at most 1e-15.  They start from
 // the root for the same fluid without rest mass (n = 0, p = (gamma - 1) e), the
 // smaller root of (gamma - 1)|M| v^2 - gamma E v + |M| = 0, which lies in the
 // bracket and is exact when N = 0.
@@ -242,11 +242,14 @@ __device__ inline void recover_ideal(double E, double Mx, double My, double Mz, 
         if (g == 0.0) break;
         if (g > 0.0) hi = v;
         else lo = v;
-        double vn = v - g * fast_rcp(dg);
-        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
-        const double dv = fabs(vn - v);
-        v = vn;
-        if (dv <= 1e-15 * v) break;
+        const double vn = v - g * fast_rcp(dg);
+        // converged: tested before the bracket, since a step below the rounding
+        // of v lands on v itself, the end of the bracket just moved there
+        if (fabs(vn - v) <= 1e-15 * v) {
+            v = vn;
+            break;
+        }
+        v = vn > lo && vn < hi ? vn : 0.5 * (lo + hi);
     }
     kap = v / M;
     e = E - M * v;

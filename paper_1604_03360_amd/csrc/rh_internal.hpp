@@ -161,6 +161,7 @@ struct StageGrid {
     int limiter;            // MUSTA-FORCE: MUSCL slope limiter (RH_LIMITER_*)
     int mk;                 // MUSTA-FORCE: FORCE evaluations per face
     T lam;                  // MUSTA-FORCE: dt/dx of the local predictor-corrector
+    int rblk0;              // ideal gas: first block of this grid in the recovery pass
 };
 
 template <class T>
@@ -175,7 +176,20 @@ struct StageArgs {
     const StageGrid<T>* grids;   // device table (ngrid > 0), sorted by blk0
     int ngrid;              // 0: single grid in `one`
     StageGrid<T> one;
+    T* prim;                // ideal gas: per-cell (vx, vy, vz, p, c_s^2) of the stage input, in
+                            // the state layout (written by the recovery pass, read by the stage)
 };
+
+// Blocks of 256 cells of the ideal-gas recovery pass for one grid.
+template <class T>
+long long recover_blocks(const StageGrid<T>& g) {
+    return ((long long)g.n[0] * g.n[1] * g.n[2] + 255) / 256;
+}
+// The ideal-gas recovery pass: A.prim <- (vx, vy, vz, p, c_s^2) of every cell of
+// A.us (FP64 Newton recovery, stored in the plan precision), floors counted once
+// per cell; nblocks is the sum of recover_blocks over the grids (ordered by rblk0).
+template <class T>
+hipError_t launch_recover_ideal(const StageArgs<T>& a, long long nblocks, hipStream_t s);
 
 // Tile width along x of the fused stage (16 or 32; 256 / tx rows along y).
 constexpr int kStageTiles[2] = {16, 32};

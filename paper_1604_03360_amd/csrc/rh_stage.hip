@@ -25,8 +25,10 @@
 // Lax-Friedrichs splitting (LOCAL: the block stages the physical flux and the
 // state of each cell with its largest characteristic speed, and every face
 // reconstructs F +- alpha u with alpha the largest speed of its 2R stencil
-// cells), and the ideal-gas equation of state (EOS_IDEAL: Newton recovery of
-// the speed).  An axis of one cell contributes nothing to L.
+// cells), and the ideal-gas equation of state (EOS_IDEAL: a recovery pass
+// solves for every cell's velocity and pressure once per evaluation of L, and
+// the stage reads them with the state).  An axis of one cell contributes
+// nothing to L.
 #include "rh_internal.hpp"
 #include "../../include/rh.h"
 
@@ -58,22 +60,6 @@ template <class T, int ORDER, int TX, bool LOCAL>
 struct StageMinBlocks {
     static constexpr int value = sizeof(T) == 4 ? 3 : (ORDER == 5 && TX == 16 && !LOCAL ? 2 : 1);
 };
-
-// Per-cell quantities of the stage for the fluid of EOS: v_d = kap * Ms_d,
-// pressure, and (for the local splitting) c_s^2 and the energy density.
-template <int EOS>
-__device__ __forceinline__ void stage_recover(const double u[5], double gm1, double& kap, double& Mxs,
-                                              double& Mys, double& Mzs, double& p, double& cs2,
-                                              unsigned& clamped) {
-    if constexpr (EOS == EOS_CONFORMAL) {
-        recover_kp3(u[0], u[1], u[2], u[3], kap, Mxs, Mys, Mzs, p, clamped);
-        cs2 = 1.0 / 3.0;
-    } else {
-        double e;
-        recover_ideal(u[0], u[1], u[2], u[3], u[4], gm1, kap, Mxs, Mys, Mzs, p, e, clamped);
-        cs2 = e + p > 0.0 ? (gm1 + 1.0) * p / (e + p) : 0.0;
-    }
-}
 
 // One face from the staged pairs of its 2R stencil cells: global splitting
 // stages (F + u, F - u) and reconstructs them directly; local splitting stages
@@ -178,10 +164,19 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     auto fetch_halo = [&](int m, T u[5]) {
         if (hkind) stage_load<T, HUB>(G, us, F, t, hxc, hyc, m, u);
     };
+    // ideal gas: the recovery pass's (vx, vy, vz, p, c_s^2) of the same cells
+    const T* pr = EOS == EOS_IDEAL ? A.prim + G.off : nullptr;
+    auto fetch_own_prim = [&](int m, T q[5]) {
+        if constexpr (EOS == EOS_IDEAL) stage_load<T, false>(G, pr, F, t, cx, cy, m, q);
+    };
+    auto fetch_halo_prim = [&](int m, T q[5]) {
+        if constexpr (EOS == EOS_IDEAL) {
+            if (hkind) stage_load<T, false>(G, pr, F, t, hxc, hyc, m, q);
+        }
+    };
 
     const T eps2 = (T)4 * G.eps;   // epsilon of the doubled split fluxes
     const T hxinv = (T)0.5 * G.inv_h[0], hyinv = (T)0.5 * G.inv_h[1], hzinv = (T)0.5 * G.inv_h[2];
-    const double gm1 = G.gm1;
     unsigned clamped = 0;
 
     T zp[5][W], zm[5][W];     // z window: staged pairs of cells k - R .. k + R - 1
@@ -200,17 +195,39 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     // Enter plane m: recover the own cell, shift its z split fluxes into the
     // window and, for an owned plane, stage the x / y split fluxes of the own
     // and halo cells.
-    auto enter = [&](int m, const T u[5], const T hu[5], bool owned) {
-        double kap, Mxs, Mys, Mzs, p, cs2;
+    auto enter = [&](int m, const T u[5], const T hu[5], const T pu[5], const T phu[5], bool owned) {
+        // velocity, pressure (and, for the local splitting, v^2 and c_s^2) of the
+        // own cell: FP64 closed-form recovery, or read from the recovery pass
+        T VX, VY, VZ, P;
+        double vxd, vyd, vzd, v2 = 0.0, cs2 = 0.0;
         unsigned c0 = 0;
-        {
-            const double ud[5] = {(double)u[0], (double)u[1], (double)u[2], (double)u[3], (double)u[4]};
-            stage_recover<EOS>(ud, gm1, kap, Mxs, Mys, Mzs, p, cs2, c0);
+        if constexpr (EOS == EOS_IDEAL) {
+            VX = pu[0];
+            VY = pu[1];
+            VZ = pu[2];
+            P = pu[3];
+            vxd = (double)VX;
+            vyd = (double)VY;
+            vzd = (double)VZ;
+            if constexpr (LOCAL) {
+                v2 = vxd * vxd + vyd * vyd + vzd * vzd;
+                cs2 = (double)pu[4];
+            }
+        } else {
+            double kap, Mxs, Mys, Mzs, p;
+            recover_kp3((double)u[0], (double)u[1], (double)u[2], (double)u[3], kap, Mxs, Mys, Mzs, p, c0);
+            vxd = kap * Mxs;
+            vyd = kap * Mys;
+            vzd = kap * Mzs;
+            VX = (T)vxd;
+            VY = (T)vyd;
+            VZ = (T)vzd;
+            P = (T)p;
+            cs2 = 1.0 / 3.0;
+            if constexpr (LOCAL) v2 = kap * kap * (Mxs * Mxs + Mys * Mys + Mzs * Mzs);
         }
-        const T P = (T)p;
-        const double v2 = LOCAL ? kap * kap * (Mxs * Mxs + Mys * Mys + Mzs * Mzs) : 0.0;
         T fp[5], fm[5];
-        stage_pair<T, 2, LOCAL>(u, (T)(kap * Mzs), P, fp, fm);
+        stage_pair<T, 2, LOCAL>(u, VZ, P, fp, fm);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
 #pragma unroll
@@ -224,58 +241,76 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
         if constexpr (LOCAL) {
 #pragma unroll
             for (int j = 0; j < W - 1; ++j) zsp[j] = zsp[j + 1];
-            zsp[W - 1] = (T)max_char_speed(kap * Mzs, v2, cs2);
+            zsp[W - 1] = (T)max_char_speed(vzd, v2, cs2);
         }
         if (!owned) return;
         if (act) {
             clamped += c0;   // floors counted once per owned cell and evaluation of L
-            stage_pair<T, 0, LOCAL>(u, (T)(kap * Mxs), P, fp, fm);
+            stage_pair<T, 0, LOCAL>(u, VX, P, fp, fm);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 sx[0][c][ly][R + lx] = fp[c];
                 sx[1][c][ly][R + lx] = fm[c];
             }
-            stage_pair<T, 1, LOCAL>(u, (T)(kap * Mys), P, fp, fm);
+            stage_pair<T, 1, LOCAL>(u, VY, P, fp, fm);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 sy[0][c][R + ly][lx] = fp[c];
                 sy[1][c][R + ly][lx] = fm[c];
             }
             if constexpr (LOCAL) {
-                ssx[ly][R + lx] = (T)max_char_speed(kap * Mxs, v2, cs2);
-                ssy[R + ly][lx] = (T)max_char_speed(kap * Mys, v2, cs2);
+                ssx[ly][R + lx] = (T)max_char_speed(vxd, v2, cs2);
+                ssy[R + ly][lx] = (T)max_char_speed(vyd, v2, cs2);
             }
         }
         if (hkind) {
-            double hk, hMx, hMy, hMz, hp, hcs2;
-            unsigned hcl = 0;
-            {
-                const double hd[5] = {(double)hu[0], (double)hu[1], (double)hu[2], (double)hu[3], (double)hu[4]};
-                if constexpr (EOS == EOS_CONFORMAL && !LOCAL) {
-                    recover_kp(hd[0], hd[1], hd[2], hd[3], hk, hMx, hMy, hp, hcl);
-                    hMz = 0.0;
-                    hcs2 = 0.0;
-                } else {
-                    stage_recover<EOS>(hd, gm1, hk, hMx, hMy, hMz, hp, hcs2, hcl);
+            T HX, HY, HP;
+            double hxd, hyd, hv2 = 0.0, hcs2 = 0.0;
+            if constexpr (EOS == EOS_IDEAL) {
+                HX = phu[0];
+                HY = phu[1];
+                HP = phu[3];
+                hxd = (double)HX;
+                hyd = (double)HY;
+                if constexpr (LOCAL) {
+                    const double hzd = (double)phu[2];
+                    hv2 = hxd * hxd + hyd * hyd + hzd * hzd;
+                    hcs2 = (double)phu[4];
                 }
+            } else {
+                double hk, hMx, hMy, hp;
+                unsigned hcl = 0;
+                if constexpr (!LOCAL) {
+                    recover_kp((double)hu[0], (double)hu[1], (double)hu[2], (double)hu[3], hk, hMx, hMy, hp, hcl);
+                } else {
+                    double hMz;
+                    recover_kp3((double)hu[0], (double)hu[1], (double)hu[2], (double)hu[3], hk, hMx, hMy, hMz, hp,
+                                hcl);
+                    hv2 = hk * hk * (hMx * hMx + hMy * hMy + hMz * hMz);
+                    hcs2 = 1.0 / 3.0;
+                }
+                hxd = hk * hMx;
+                hyd = hk * hMy;
+                HX = (T)hxd;
+                HY = (T)hyd;
+                HP = (T)hp;
             }
-            const double hv2 = LOCAL ? hk * hk * (hMx * hMx + hMy * hMy + hMz * hMz) : 0.0;
             if (hkind == 1) {
-                stage_pair<T, 0, LOCAL>(hu, (T)(hk * hMx), (T)hp, fp, fm);
+                stage_pair<T, 0, LOCAL>(hu, HX, HP, fp, fm);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     sx[0][c][hr][hc] = fp[c];
                     sx[1][c][hr][hc] = fm[c];
                 }
-                if constexpr (LOCAL) ssx[hr][hc] = (T)max_char_speed(hk * hMx, hv2, hcs2);
+                if constexpr (LOCAL) ssx[hr][hc] = (T)max_char_speed(hxd, hv2, hcs2);
             } else {
-                stage_pair<T, 1, LOCAL>(hu, (T)(hk * hMy), (T)hp, fp, fm);
+                stage_pair<T, 1, LOCAL>(hu, HY, HP, fp, fm);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     sy[0][c][hr][hc] = fp[c];
                     sy[1][c][hr][hc] = fm[c];
                 }
-                if constexpr (LOCAL) ssy[hr][hc] = (T)max_char_speed(hk * hMy, hv2, hcs2);
+                if constexpr (LOCAL) ssy[hr][hc] = (T)max_char_speed(hyd, hv2, hcs2);
             }
         }
     };
@@ -385,18 +420,26 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
 
     // fill: planes k0 - R .. k0 + R - 1 (the z window of face k0 - 1/2)
     T nu[5], nh[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+    T npu[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, nph[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
     fetch_own(k0 - R, nu);
+    fetch_own_prim(k0 - R, npu);
     for (int m = k0 - R; m < k0 + R; ++m) {
-        T u[5], hu[5];
+        T u[5], hu[5], pu[5], phu[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             u[f] = nu[f];
             hu[f] = nh[f];
+            pu[f] = npu[f];
+            phu[f] = nph[f];
         }
         const bool owned = m >= k0 && m < kend;
         fetch_own(m + 1, nu);
-        if (m + 1 >= k0 && m + 1 < kend) fetch_halo(m + 1, nh);
-        enter(m, u, hu, owned);
+        fetch_own_prim(m + 1, npu);
+        if (m + 1 >= k0 && m + 1 < kend) {
+            fetch_halo(m + 1, nh);
+            fetch_halo_prim(m + 1, nph);
+        }
+        enter(m, u, hu, pu, phu, owned);
         if (owned) plane_xy();
         else if (m >= k0) push_none();
     }
@@ -407,17 +450,25 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     // main loop: plane m = k + R enters, cell k is finished
     for (int k = k0; k < kend; ++k) {
         const int m = k + R;
-        T u[5], hu[5];
+        T u[5], hu[5], pu[5], phu[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             u[f] = nu[f];
             hu[f] = nh[f];
+            pu[f] = npu[f];
+            phu[f] = nph[f];
         }
         const bool owned = m < kend;
-        if (k + 1 < kend) fetch_own(m + 1, nu);
-        if (m + 1 < kend) fetch_halo(m + 1, nh);
+        if (k + 1 < kend) {
+            fetch_own(m + 1, nu);
+            fetch_own_prim(m + 1, npu);
+        }
+        if (m + 1 < kend) {
+            fetch_halo(m + 1, nh);
+            fetch_halo_prim(m + 1, nph);
+        }
         const uint32_t off = cb + (uint32_t)k * sb;
-        enter(m, u, hu, owned);
+        enter(m, u, hu, pu, phu, owned);
         T Lk[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -450,6 +501,51 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     }
     if (clamped) atomicAdd(A.clamps, clamped);
 }
+
+// Ideal-gas recovery pass: every cell of every grid once per evaluation of L
+// (the stage kernel reads the result for its own and halo cells, so the Newton
+// iteration runs once per cell instead of once per staging).
+template <class T>
+__global__ void __launch_bounds__(256) recover_ideal_cells(StageArgs<T> A) {
+    const int b = (int)blockIdx.x;
+    int g = 0;
+    if (A.ngrid > 0) {
+        int lo = 0, hi = A.ngrid - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.grids[mid].rblk0 <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        g = lo;
+    }
+    const StageGrid<T>& G = A.ngrid > 0 ? A.grids[g] : A.one;
+    const long long n = (long long)G.n[0] * G.n[1] * G.n[2];
+    const long long i = (long long)(b - G.rblk0) * 256 + threadIdx.x;
+    unsigned cl = 0;
+    if (i < n) {
+        const T* u = A.us + G.off;
+        T* q = A.prim + G.off;
+        double kap, Mxs, Mys, Mzs, p, e;
+        recover_ideal((double)u[i], (double)u[n + i], (double)u[2 * n + i], (double)u[3 * n + i],
+                      (double)u[4 * n + i], G.gm1, kap, Mxs, Mys, Mzs, p, e, cl);
+        q[i] = (T)(kap * Mxs);
+        q[n + i] = (T)(kap * Mys);
+        q[2 * n + i] = (T)(kap * Mzs);
+        q[3 * n + i] = (T)p;
+        q[4 * n + i] = (T)(e + p > 0.0 ? (G.gm1 + 1.0) * p / (e + p) : 0.0);
+    }
+    if (cl) atomicAdd(A.clamps, cl);
+}
+
+template <class T>
+hipError_t launch_recover_ideal(const StageArgs<T>& a, long long nblocks, hipStream_t s) {
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    recover_ideal_cells<T><<<dim3((unsigned)nblocks), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_recover_ideal<float>(const StageArgs<float>&, long long, hipStream_t);
+template hipError_t launch_recover_ideal<double>(const StageArgs<double>&, long long, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Host side
