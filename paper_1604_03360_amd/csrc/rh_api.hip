@@ -14,6 +14,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/rh.h"
 #include "rh_internal.hpp"
 
@@ -36,6 +38,16 @@ rh_status fail(rh_status code, const std::string& msg) {
 rh_status hip_fail(hipError_t e, const char* what) {
     return fail(RH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+// roctx range over one library call (host side: enqueue, and the waits of the
+// calls that synchronise), visible to rocprofv3 --marker-trace; a push / pop
+// pair costs a few tens of nanoseconds when no tool is attached.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePush(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Device address of `scratch` on each device, looked up on the first
 // rh_totals_noalloc call made with that device current.
@@ -213,7 +225,7 @@ bool adjoint_supported(const rh_grid_desc& d) { return !needs_stage(d); }
 template <class T>
 hipError_t launch_stage_of(const rh_grid_desc& d, int tx, bool hub, const rh::StageArgs<T>& sa,
                            long long nblocks, hipStream_t s) {
-    if (d.scheme == RH_SCHEME_MUSTA) return rh::launch_musta<T>(hub, d.eos, sa, nblocks, s);
+    if (d.scheme == RH_SCHEME_MUSTA) return rh::launch_musta<T>(hub, d.eos, d.limiter, d.musta_stages, sa, nblocks, s);
     return rh::launch_stage<T>(d.scheme, tx, hub, d.flux_split == RH_SPLIT_LOCAL, d.eos, sa, nblocks, s);
 }
 
@@ -318,9 +330,19 @@ rh_status one_step(rh_plan* p, double dt, double t, T* stages) {
     T* U1 = stages ? stages : (T*)p->ws;   // stage states go to the caller's store if given
     T* U2 = U1 + S;
     T* Lc = (T*)p->ws + 2 * S;
-    rh_status st = evaluate<T>(p, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
-    if (st == RH_OK) st = evaluate<T>(p, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2);
-    if (st == RH_OK) st = evaluate<T>(p, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3);
+    rh_status st;
+    {
+        TraceRange r("rh stage 1");
+        st = evaluate<T>(p, U0, U0, Lc, U1, t, dt, rh::STAGE_1);
+    }
+    if (st == RH_OK) {
+        TraceRange r("rh stage 2");
+        st = evaluate<T>(p, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2);
+    }
+    if (st == RH_OK) {
+        TraceRange r("rh stage 3");
+        st = evaluate<T>(p, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3);
+    }
     return st;
 }
 
@@ -523,6 +545,7 @@ rh_status rh_get_fields(rh_plan* p, double* dst, int kind) {
 }
 
 rh_status rh_apply_L(rh_plan* p, double t, void* L_out) {
+    TraceRange trace("rh_apply_L");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!L_out) return fail(RH_E_INVAL, "L_out is NULL");
@@ -540,6 +563,7 @@ rh_status rh_apply_L(rh_plan* p, double t, void* L_out) {
 }
 
 rh_status rh_step(rh_plan* p, double dt, int n_steps, double* t_inout) {
+    TraceRange trace("rh_step");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!t_inout) return fail(RH_E_INVAL, "t_inout is NULL");
@@ -597,6 +621,7 @@ rh_status rh_get_stage_tuning(const rh_plan* p, int* tile_x, int* seg_z) {
 }
 
 rh_status rh_totals(rh_plan* p, double out[5], long long counters[2]) {
+    TraceRange trace("rh_totals");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!out) return fail(RH_E_INVAL, "out is NULL");
@@ -884,9 +909,19 @@ rh_status batch_one_step(rh_batch* b, hipStream_t s, double t, double dt) {
     T* U2 = U1 + S;
     T* Lc = U2 + S;
     // the stage path leaves Lc unused: the ideal gas's recovered fields go there
-    rh_status st = batch_evaluate<T>(b, s, U0, U0, Lc, U1, t, dt, rh::STAGE_1, Lc);
-    if (st == RH_OK) st = batch_evaluate<T>(b, s, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2, Lc);
-    if (st == RH_OK) st = batch_evaluate<T>(b, s, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3, Lc);
+    rh_status st;
+    {
+        TraceRange r("rh batch stage 1");
+        st = batch_evaluate<T>(b, s, U0, U0, Lc, U1, t, dt, rh::STAGE_1, Lc);
+    }
+    if (st == RH_OK) {
+        TraceRange r("rh batch stage 2");
+        st = batch_evaluate<T>(b, s, U1, U0, Lc, U2, t + dt, dt, rh::STAGE_2, Lc);
+    }
+    if (st == RH_OK) {
+        TraceRange r("rh batch stage 3");
+        st = batch_evaluate<T>(b, s, U2, U0, Lc, U0, t + 0.5 * dt, dt, rh::STAGE_3, Lc);
+    }
     return st;
 }
 
@@ -1087,6 +1122,7 @@ rh_status rh_batch_get_fields(rh_batch* b, double* dst, int kind) {
 }
 
 rh_status rh_batch_step(rh_batch* b, double dt, int n_steps, double* t_inout) {
+    TraceRange trace("rh_batch_step");
     rh_status st = check_batch(b);
     if (st != RH_OK) return st;
     if (!t_inout) return fail(RH_E_INVAL, "t_inout is NULL");
@@ -1099,6 +1135,7 @@ rh_status rh_batch_step(rh_batch* b, double dt, int n_steps, double* t_inout) {
 }
 
 rh_status rh_batch_totals(rh_batch* b, double* out, long long counters[2]) {
+    TraceRange trace("rh_batch_totals");
     rh_status st = check_batch(b);
     if (st != RH_OK) return st;
     if (!out) return fail(RH_E_INVAL, "out is NULL");
@@ -1196,6 +1233,7 @@ rh_status rh_batch_get_tuning(const rh_batch* b, int* tile_x, int* seg_y, int* s
 }
 
 rh_status rh_batch_autotune(rh_batch* b, int reps) {
+    TraceRange trace("rh_batch_autotune");
     rh_status st = check_batch(b);
     if (st != RH_OK) return st;
     if (reps < 1) return fail(RH_E_INVAL, "reps must be >= 1");
@@ -1510,6 +1548,7 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 extern "C" {
 
 rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void* out) {
+    TraceRange trace("rh_apply_vjp");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!adjoint_supported(p->d))
@@ -1528,6 +1567,7 @@ rh_status rh_apply_vjp(rh_plan* p, double t, const void* u, const void* w, void*
 }
 
 rh_status rh_step_store(rh_plan* p, double dt, double* t_inout, void* stages) {
+    TraceRange trace("rh_step_store");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!t_inout || !stages) return fail(RH_E_INVAL, "NULL argument");
@@ -1543,6 +1583,7 @@ rh_status rh_step_store(rh_plan* p, double dt, double* t_inout, void* stages) {
 
 rh_status rh_step_vjp_stored(rh_plan* p, double t, double dt, const void* u_n, const void* stages,
                              const void* ubar_in, void* ubar_out, void* scratch) {
+    TraceRange trace("rh_step_vjp_stored");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!adjoint_supported(p->d))
@@ -1576,6 +1617,7 @@ size_t rh_vjp_workspace_bytes(const rh_plan* p) { return p ? 3 * rh_state_bytes(
 
 rh_status rh_step_vjp(rh_plan* p, double t, double dt, const void* u_n, const void* ubar_in,
                       void* ubar_out, void* scratch) {
+    TraceRange trace("rh_step_vjp");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
     if (!adjoint_supported(p->d))

@@ -217,7 +217,10 @@ template <class T>
 void musta_shape(StageGrid<T>& g, int seg);
 int musta_default_segment(const int n[3]);
 template <class T>
-hipError_t launch_musta(bool hub, int eos, const StageArgs<T>& a, long long nblocks, hipStream_t s);
+// limiter (RH_LIMITER_*) and mk (FORCE evaluations per face) are those of
+// every grid of the launch (they select the kernel instance).
+hipError_t launch_musta(bool hub, int eos, int limiter, int mk, const StageArgs<T>& a, long long nblocks,
+                        hipStream_t s);
 
 // The chip hands consecutive blocks of a launch to its eight XCDs in turn
 // (block b to XCD b mod 8).  Renumbering gives every XCD a contiguous range of

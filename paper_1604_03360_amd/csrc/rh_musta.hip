@@ -31,10 +31,16 @@ constexpr int TX = kMustaTX, TY = kMustaTY;
 constexpr int G = 2;                 // ghost cells per side (MUSCL slopes of the end faces)
 constexpr int SX = TX + 2 * G, SY = TY + 2 * G;
 
+// Limiter and stage count of a kernel instance: fixed at compile time for the
+// default scheme (minmod, two stages: straight-line face code), read from the
+// grid entry otherwise.
+constexpr int kAnyLimiter = -1, kAnyStages = 0;
+
 // Limited MUSCL slope from the one-sided differences a, b (zero where they
 // differ in sign): minmod, MC, van Leer, superbee, or none.
-template <class T>
-__device__ __forceinline__ T limited_slope(int lim, T a, T b) {
+template <class T, int LIM>
+__device__ __forceinline__ T limited_slope(int rt_lim, T a, T b) {
+    const int lim = LIM == kAnyLimiter ? rt_lim : LIM;
     if (lim == RH_LIMITER_NONE) return (T)0;
     if (!((a > (T)0 && b > (T)0) || (a < (T)0 && b < (T)0))) return (T)0;
     const T aa = fabs(a), ab = fabs(b);
@@ -67,20 +73,22 @@ __device__ __forceinline__ void phys_flux(const T u[5], double gm1, T f[5], unsi
 }
 
 // MUSCL + MUSTA flux of face i+1/2 from the cells i-1 .. i+2 (a, b, c, d).
-template <class T, int DIR, int EOS>
+template <class T, int DIR, int EOS, int LIM, int MK>
 __device__ __forceinline__ void musta_face(const T a[5], const T b[5], const T c[5], const T d[5],
                                            const StageGrid<T>& Gr, T F[5], unsigned& cl) {
     T uL[5], uR[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        const T si = limited_slope<T>(Gr.limiter, b[q] - a[q], c[q] - b[q]);
-        const T sj = limited_slope<T>(Gr.limiter, c[q] - b[q], d[q] - c[q]);
+        const T si = limited_slope<T, LIM>(Gr.limiter, b[q] - a[q], c[q] - b[q]);
+        const T sj = limited_slope<T, LIM>(Gr.limiter, c[q] - b[q], d[q] - c[q]);
         uL[q] = b[q] + (T)0.5 * si;
         uR[q] = c[q] - (T)0.5 * sj;
     }
     const T lam = Gr.lam, hlam = (T)0.5 * Gr.lam, q4 = (T)1 / ((T)4 * Gr.lam);
-#pragma unroll 1
-    for (int st = 1; st <= Gr.mk; ++st) {
+    const int mk = MK == kAnyStages ? Gr.mk : MK;
+    constexpr int kUnroll = MK == kAnyStages ? 1 : MK;
+#pragma unroll kUnroll
+    for (int st = 1; st <= mk; ++st) {
         T fL[5], fR[5], uM[5], fM[5];
         phys_flux<T, DIR, EOS>(uL, Gr.gm1, fL, cl);
         phys_flux<T, DIR, EOS>(uR, Gr.gm1, fR, cl);
@@ -89,7 +97,7 @@ __device__ __forceinline__ void musta_face(const T a[5], const T b[5], const T c
         phys_flux<T, DIR, EOS>(uM, Gr.gm1, fM, cl);
 #pragma unroll
         for (int q = 0; q < 5; ++q) F[q] = (T)0.25 * (fL[q] + (T)2 * fM[q] + fR[q]) - (uR[q] - uL[q]) * q4;
-        if (st < Gr.mk) {
+        if (st < mk) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
                 uL[q] = uL[q] - lam * (F[q] - fL[q]);
@@ -106,7 +114,7 @@ struct MustaMinBlocks {
     static constexpr int value = sizeof(T) == 4 ? 2 : 1;
 };
 
-template <class T, bool HUB, int EOS>
+template <class T, bool HUB, int EOS, int LIM, int MK>
 __global__ void __launch_bounds__(256, (MustaMinBlocks<T>::value)) stage_musta(StageArgs<T> A) {
     __shared__ T su[5][SY][SX];           // staged plane: rows -2 .. TY+1, columns -2 .. TX+1
     __shared__ T fxs[5][TY][TX + 1];      // x faces: column f = face between tile columns f-1 and f
@@ -221,7 +229,7 @@ __global__ void __launch_bounds__(256, (MustaMinBlocks<T>::value)) stage_musta(S
                         d[c] = su[c][r + G][f + 3];
                     }
                     unsigned cl = 0;
-                    musta_face<T, 0, EOS>(a, bb, c2, d, Gr, Fx, cl);
+                    musta_face<T, 0, EOS, LIM, MK>(a, bb, c2, d, Gr, Fx, cl);
                     if (f > 0 || x0 == 0) clamped += cl;   // each face of the grid counted once
 #pragma unroll
                     for (int c = 0; c < 5; ++c) fxs[c][r][f] = Fx[c];
@@ -240,7 +248,7 @@ __global__ void __launch_bounds__(256, (MustaMinBlocks<T>::value)) stage_musta(S
                         d[c] = su[c][f + 3][col + G];
                     }
                     unsigned cl = 0;
-                    musta_face<T, 1, EOS>(a, bb, c2, d, Gr, Fy, cl);
+                    musta_face<T, 1, EOS, LIM, MK>(a, bb, c2, d, Gr, Fy, cl);
                     if (f > 0 || y0 == 0) clamped += cl;
 #pragma unroll
                     for (int c = 0; c < 5; ++c) fys[c][f][col] = Fy[c];
@@ -261,7 +269,7 @@ __global__ void __launch_bounds__(256, (MustaMinBlocks<T>::value)) stage_musta(S
             T Fz[5];
             if (doz) {
                 unsigned cl = 0;
-                musta_face<T, 2, EOS>(zw[0], zw[1], zw[2], zw[3], Gr, Fz, cl);
+                musta_face<T, 2, EOS, LIM, MK>(zw[0], zw[1], zw[2], zw[3], Gr, Fz, cl);
                 if (act && (m - 2 >= k0 || k0 == 0)) clamped += cl;
             } else {
 #pragma unroll
@@ -325,24 +333,32 @@ void musta_shape(StageGrid<T>& g, int seg) {
     g.nseg = (g.n[2] + seg - 1) / seg;
 }
 
-template <class T>
-hipError_t launch_musta(bool hub, int eos, const StageArgs<T>& a, long long nblocks, hipStream_t s) {
-    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nblocks);
+template <class T, int LIM, int MK>
+hipError_t launch_musta_t(bool hub, int eos, const StageArgs<T>& a, const dim3 grid, hipStream_t s) {
     if (eos == EOS_CONFORMAL) {
-        if (hub) stage_musta<T, true, EOS_CONFORMAL><<<grid, 256, 0, s>>>(a);
-        else stage_musta<T, false, EOS_CONFORMAL><<<grid, 256, 0, s>>>(a);
+        if (hub) stage_musta<T, true, EOS_CONFORMAL, LIM, MK><<<grid, 256, 0, s>>>(a);
+        else stage_musta<T, false, EOS_CONFORMAL, LIM, MK><<<grid, 256, 0, s>>>(a);
     } else if (eos == EOS_IDEAL && !hub) {
-        stage_musta<T, false, EOS_IDEAL><<<grid, 256, 0, s>>>(a);
+        stage_musta<T, false, EOS_IDEAL, LIM, MK><<<grid, 256, 0, s>>>(a);
     } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_musta(bool hub, int eos, int limiter, int mk, const StageArgs<T>& a, long long nblocks,
+                        hipStream_t s) {
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL || mk < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblocks);
+    if (limiter == RH_LIMITER_MINMOD && mk == 2)
+        return launch_musta_t<T, RH_LIMITER_MINMOD, 2>(hub, eos, a, grid, s);
+    return launch_musta_t<T, kAnyLimiter, kAnyStages>(hub, eos, a, grid, s);
+}
+
 template void musta_shape<float>(StageGrid<float>&, int);
 template void musta_shape<double>(StageGrid<double>&, int);
-template hipError_t launch_musta<float>(bool, int, const StageArgs<float>&, long long, hipStream_t);
-template hipError_t launch_musta<double>(bool, int, const StageArgs<double>&, long long, hipStream_t);
+template hipError_t launch_musta<float>(bool, int, int, int, const StageArgs<float>&, long long, hipStream_t);
+template hipError_t launch_musta<double>(bool, int, int, int, const StageArgs<double>&, long long, hipStream_t);
 
 }  // namespace rh

@@ -92,3 +92,16 @@ def test_hubble_boundaries_need_the_conformal_fluid(lib):
     with pytest.raises(rh.RHError) as ei:
         rh.rh_plan_create(d)
     assert ei.value.status == rh.RH_E_NOTSUP
+
+
+def test_library_calls_carry_roctx_ranges(lib):
+    """The compute entry points push roctx ranges (rocprofv3 --marker-trace):
+    the built library imports the push / pop pair from the roctx library."""
+    import subprocess
+    from paper_1604_03360_amd import rh
+    out = subprocess.run(["nm", "-D", "--undefined-only", rh.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    src = open(os.path.join(ROOT, "paper_1604_03360_amd", "csrc", "rh_api.hip")).read()
+    for name in ("rh_step", "rh_apply_L", "rh_batch_step", "rh_apply_vjp", "rh_step_vjp"):
+        assert 'TraceRange trace("%s")' % name in src
