@@ -195,13 +195,16 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     // Enter plane m: recover the own cell, shift its z split fluxes into the
     // window and, for an owned plane, stage the x / y split fluxes of the own
     // and halo cells.
-    auto enter = [&](int m, const T u[5], const T hu[5], const T pu[5], const T phu[5], bool owned) {
+    auto enter = [&](int m, const T u[5], const T hu[5], bool owned) {
         // velocity, pressure (and, for the local splitting, v^2 and c_s^2) of the
         // own cell: FP64 closed-form recovery, or read from the recovery pass
+        // (loaded here, not a plane ahead: the registers of a prefetch spill)
         T VX, VY, VZ, P;
         double vxd, vyd, vzd, v2 = 0.0, cs2 = 0.0;
         unsigned c0 = 0;
         if constexpr (EOS == EOS_IDEAL) {
+            T pu[5];
+            fetch_own_prim(m, pu);
             VX = pu[0];
             VY = pu[1];
             VZ = pu[2];
@@ -267,6 +270,8 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
             T HX, HY, HP;
             double hxd, hyd, hv2 = 0.0, hcs2 = 0.0;
             if constexpr (EOS == EOS_IDEAL) {
+                T phu[5];
+                fetch_halo_prim(m, phu);
                 HX = phu[0];
                 HY = phu[1];
                 HP = phu[3];
@@ -420,26 +425,18 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
 
     // fill: planes k0 - R .. k0 + R - 1 (the z window of face k0 - 1/2)
     T nu[5], nh[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
-    T npu[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, nph[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
     fetch_own(k0 - R, nu);
-    fetch_own_prim(k0 - R, npu);
     for (int m = k0 - R; m < k0 + R; ++m) {
-        T u[5], hu[5], pu[5], phu[5];
+        T u[5], hu[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             u[f] = nu[f];
             hu[f] = nh[f];
-            pu[f] = npu[f];
-            phu[f] = nph[f];
         }
         const bool owned = m >= k0 && m < kend;
         fetch_own(m + 1, nu);
-        fetch_own_prim(m + 1, npu);
-        if (m + 1 >= k0 && m + 1 < kend) {
-            fetch_halo(m + 1, nh);
-            fetch_halo_prim(m + 1, nph);
-        }
-        enter(m, u, hu, pu, phu, owned);
+        if (m + 1 >= k0 && m + 1 < kend) fetch_halo(m + 1, nh);
+        enter(m, u, hu, owned);
         if (owned) plane_xy();
         else if (m >= k0) push_none();
     }
@@ -450,25 +447,17 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
     // main loop: plane m = k + R enters, cell k is finished
     for (int k = k0; k < kend; ++k) {
         const int m = k + R;
-        T u[5], hu[5], pu[5], phu[5];
+        T u[5], hu[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
             u[f] = nu[f];
             hu[f] = nh[f];
-            pu[f] = npu[f];
-            phu[f] = nph[f];
         }
         const bool owned = m < kend;
-        if (k + 1 < kend) {
-            fetch_own(m + 1, nu);
-            fetch_own_prim(m + 1, npu);
-        }
-        if (m + 1 < kend) {
-            fetch_halo(m + 1, nh);
-            fetch_halo_prim(m + 1, nph);
-        }
+        if (k + 1 < kend) fetch_own(m + 1, nu);
+        if (m + 1 < kend) fetch_halo(m + 1, nh);
         const uint32_t off = cb + (uint32_t)k * sb;
-        enter(m, u, hu, pu, phu, owned);
+        enter(m, u, hu, owned);
         T Lk[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
