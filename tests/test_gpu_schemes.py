@@ -272,6 +272,63 @@ def test_ideal_gas_shock_tube(scheme):
     assert np.all(err32 <= 2e-5), err32
 
 
+@pytest.mark.parametrize("split", ["global", "local"])
+def test_ideal_gas_floors_counted_once_per_cell(split):
+    """Ideal gas, WENO5: cells below the energy floor and beyond the velocity cap.
+    L against the oracle; the floor counter counts each floored cell once per
+    evaluation of L (the recovery pass solves every cell once), as the oracle's
+    primitive recovery of the state does (its L recovers each cell once per axis)."""
+    rh = rh_module()
+    spec = inputs.with_scheme(inputs.hot_gas(inputs.random_smooth((29, 31, 17), h=0.1, seed=6)), eos=1,
+                              gamma=5.0 / 3.0, order=5, lf_local=split == "local")
+    con = _con(spec)
+    rng = np.random.default_rng(17)
+    cells = rng.choice(con[0].size, 40, replace=False)
+    flat = con.reshape(5, -1)
+    flat[0, cells[:20]] = 1e-14                     # below the energy floor
+    flat[1, cells[20:]] = 1.5 * flat[0, cells[20:]]  # beyond the velocity cap
+    h = rh.Hydro.from_spec(spec, precision=rh.RH_PREC_FP64)
+    h.set_conserved(con)
+    got = h.apply_L(0.0).double().cpu().numpy()
+    _, cnt = h.totals()
+    h.close()
+    grid = oracle.grid_from_spec(spec)
+    ref, clamps = oracle.apply_L(grid, con, 0.0, return_clamps=True)
+    _, floored = oracle.con2prim_eos(grid, con, return_clamps=True)
+    err = L_errors(got, ref, con, min(spec["h"]))
+    print("ideal floors", split, err, cnt, floored, clamps, flush=True)
+    assert floored == 40 and clamps == 3 * floored and cnt[0] == floored
+    assert np.all(err <= FP64_TOL), err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ideal_gas_batch_equals_single_grids(precision):
+    """Grids of different sizes in one batch: the recovery pass finds each block's
+    grid in its own block table; three steps bitwise equal to single-grid runs,
+    also after autotuning the batch (the tuning runs the recovery pass too)."""
+    import torch
+    rh = rh_module()
+    prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
+    for lf_local in (False, True):
+        specs = [inputs.with_scheme(inputs.hot_gas(inputs.hotspots(k, size=s)), eos=1, gamma=5.0 / 3.0,
+                                    lf_local=lf_local) for k, s in ((0, 24), (1, 40), (2, 17))]
+        b = rh.Batch(specs, precision=prec)
+        b.set_primitive([sp["prim"] for sp in specs])
+        if lf_local:
+            rh.rh_batch_autotune(b.batch, 1)
+        rh.rh_batch_set_graph(b.batch, 1)
+        b.step(specs[0]["dt"], 3)
+        got = b.get()
+        b.close()
+        for sp, g in zip(specs, got):
+            h = _hydro(rh, sp, prec)
+            h.step(sp["dt"], 3)
+            single = h.get()
+            h.close()
+            assert np.array_equal(g, single)
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------------------
 # Paths and errors
 # ---------------------------------------------------------------------------
