@@ -66,7 +66,7 @@ typedef int rh_status;
 #define RH_KERNEL_SWEEP_X 0   /* x-direction WENO sweep */
 #define RH_KERNEL_SWEEP_Y 1   /* y-direction WENO sweep */
 #define RH_KERNEL_SWEEP_Z 2   /* z-direction WENO sweep */
-#define RH_KERNEL_OTHER   3   /* combine, conversion and reduction kernels */
+#define RH_KERNEL_OTHER   3   /* combine, conversion, reduction and ideal-gas recovery kernels */
 #define RH_KERNEL_ADJOINT 4   /* adjoint sweeps (all axes) */
 #define RH_KERNEL_SWEEP_XY 5  /* fused x and y sweep (WENO5, and WENO7 in FP32; periodic x of
                                  64..256 cells, a multiple of 64): one launch in place of the x
