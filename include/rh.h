@@ -225,6 +225,11 @@ rh_status rh_step(rh_plan* plan, double dt, int n_steps, double* t_inout);
  * Errors: RH_E_STATE, RH_E_HIP, RH_E_PHYS (strict plans only). */
 rh_status rh_totals(rh_plan* plan, double out[5], long long counters[2]);
 
+/* The integrals of E, Mx, My, Mz and N over the grid (the conserved charges of
+ * Eq. (1)): the sums of rh_totals times the cell volume dx dy dz.  counters,
+ * synchronisation and errors as rh_totals (on RH_E_PHYS out is still filled). */
+rh_status rh_totals_integrated(rh_plan* plan, double out[5], long long counters[2]);
+
 /* Replay steps from a graph (enable != 0): rh_step then captures one SSP-RK3
  * step (its sweep launches, Sec. 1) into a hipGraph on first use and launches
  * that graph once per step; the graph is rebuilt when dt or the bound buffers
@@ -325,6 +330,19 @@ rh_status rh_step_vjp(rh_plan* plan, double t, double dt, const void* u_n, const
  * Errors: RH_E_STATE (unbound), RH_E_INVAL (NULL, dt <= 0, aliasing). */
 rh_status rh_step_store(rh_plan* plan, double dt, double* t_inout, void* stages);
 
+/* n_steps SSP-RK3 steps of the bound state (bitwise as rh_step with the same
+ * n_steps) that keep, for every step k, the state it started from and its two
+ * stage states: store is a caller-owned device buffer of 3 * n_steps states,
+ * [n_steps][3][5][nz][ny][nx] = (u_k, u1_k, u2_k), so that step k's adjoint is
+ * rh_step_vjp_stored(plan, t_k, dt, store_k, store_k + one state, ...) with t_k
+ * the time of step k as rh_step takes it (*t_inout on entry with dt added k
+ * times).  *t_inout advances by n_steps * dt, as in rh_step; n_steps == 0 is a
+ * no-op.  Asynchronous on the bound stream (the steps run eagerly, not from the
+ * step graph; a failed call leaves the steps before it done and *t_inout
+ * unchanged).  Errors: RH_E_STATE (unbound), RH_E_INVAL (NULL, dt <= 0,
+ * n_steps < 0, store aliasing the bound state or workspace). */
+rh_status rh_step_store_n(rh_plan* plan, double dt, int n_steps, double* t_inout, void* store);
+
 /* The adjoint of rh_step_vjp with the stage states supplied instead of
  * recomputed: stages holds u1, u2 of the step taken from u_n at time t (as
  * written by rh_step_store), scratch is two states.  Same result as
@@ -379,6 +397,10 @@ rh_status rh_batch_step(rh_batch* batch, double dt, int n_steps, double* t_inout
 /* Per-grid FP64 totals out[n_grids][5] (E, Mx, My, Mz, N) and counters as
  * rh_totals.  Synchronises the stream. */
 rh_status rh_batch_totals(rh_batch* batch, double* out, long long counters[2]);
+
+/* Per-grid integrals out[n_grids][5]: rh_batch_totals times each grid's cell
+ * volume dx dy dz.  Errors as rh_batch_totals. */
+rh_status rh_batch_totals_integrated(rh_batch* batch, double* out, long long counters[2]);
 
 /* Enable (nonzero) or disable hipGraph capture and replay of whole steps.
  * Ignored (no graph) when any grid has a HUBBLE boundary, whose ghost values

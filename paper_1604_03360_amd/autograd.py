@@ -5,7 +5,7 @@ u0 (a device tensor of the plan's dtype and layout [5][nz][ny][nx]) by n_steps
 steps of the library's SSP-RK3 scheme and returns the final state.  The forward
 pass keeps a checkpoint of the state every ``every`` steps; the backward pass
 replays each checkpointed segment forward, keeping every step's input and its
-two Runge-Kutta stage states (``rh_step_store``), and then applies the
+two Runge-Kutta stage states (``rh_step_store_n``), and then applies the
 hand-written adjoint of one step (``rh_step_vjp_stored``) in reverse.  The
 replays run on the plan's own state buffer; backward restores that buffer and
 the plan's time to what they held when it was called, so stepping the plan
@@ -48,15 +48,16 @@ class HydroRun(torch.autograd.Function):
         for seg in reversed(range(len(ctx.checkpoints))):
             u_c, t_c = ctx.checkpoints[seg]
             steps = min(every, ctx.n_steps - seg * every)
-            states, stages = [], []
             hydro.state.copy_(u_c)
             hydro.t = t_c
-            for _ in range(steps):
-                states.append(hydro.state.clone())
-                stages.append(hydro.step_store(dt))
+            # [steps][3]: each step's input and its two stage states
+            store = hydro.step_store_n(dt, steps)
+            times = [t_c]
+            for _ in range(steps - 1):
+                times.append(times[-1] + dt)   # the step times the replay took
             for j in reversed(range(steps)):
-                ubar = hydro.step_vjp_stored(states[j], stages[j], ubar, dt, t=t_c + j * dt)
-            del states, stages
+                ubar = hydro.step_vjp_stored(store[j, 0], store[j, 1:], ubar, dt, t=times[j])
+            del store
         hydro.state.copy_(resume_state)
         hydro.t = resume_t
         return ubar, None, None, None, None

@@ -650,6 +650,14 @@ rh_status rh_totals(rh_plan* p, double out[5], long long counters[2]) {
     return RH_OK;
 }
 
+rh_status rh_totals_integrated(rh_plan* p, double out[5], long long counters[2]) {
+    const rh_status st = rh_totals(p, out, counters);
+    if (st != RH_OK && st != RH_E_PHYS) return st;
+    const double vol = p->d.dx * p->d.dy * p->d.dz;
+    for (int f = 0; f < 5; ++f) out[f] *= vol;
+    return st;
+}
+
 rh_status rh_totals_noalloc(const void* state, int precision, long long ncell, double* out_dev, void* stream) {
     if (!state || !out_dev) return fail(RH_E_INVAL, "state and out_dev must not be NULL");
     if (precision != RH_PREC_FP64 && precision != RH_PREC_FP32) return fail(RH_E_INVAL, "unknown precision");
@@ -1173,6 +1181,16 @@ rh_status rh_batch_totals(rh_batch* b, double* out, long long counters[2]) {
     return RH_OK;
 }
 
+rh_status rh_batch_totals_integrated(rh_batch* b, double* out, long long counters[2]) {
+    const rh_status st = rh_batch_totals(b, out, counters);
+    if (st != RH_OK && st != RH_E_PHYS) return st;
+    for (int i = 0; i < b->ngrid; ++i) {
+        const double vol = b->d[i].dx * b->d[i].dy * b->d[i].dz;
+        for (int f = 0; f < 5; ++f) out[5 * i + f] *= vol;
+    }
+    return st;
+}
+
 rh_status rh_batch_set_graph(rh_batch* b, int enable) {
     if (!b) return fail(RH_E_INVAL, "batch is NULL");
     b->graph_on = enable != 0;
@@ -1579,6 +1597,32 @@ rh_status rh_step_store(rh_plan* p, double dt, double* t_inout, void* stages) {
                     : step_impl<double>(p, dt, 1, *t_inout, (double*)stages);
     if (st == RH_OK) *t_inout += dt;
     return st;
+}
+
+rh_status rh_step_store_n(rh_plan* p, double dt, int n_steps, double* t_inout, void* store) {
+    TraceRange trace("rh_step_store_n");
+    rh_status st = check_bound(p);
+    if (st != RH_OK) return st;
+    if (!t_inout || !store) return fail(RH_E_INVAL, "NULL argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
+    if (n_steps < 0) return fail(RH_E_INVAL, "n_steps must be >= 0");
+    const size_t sb = rh_state_bytes(p);
+    const size_t total = 3 * sb * (size_t)n_steps;
+    if (n_steps > 0 && (overlaps(store, total, p->state, sb) || overlaps(store, total, p->ws, 3 * sb)))
+        return fail(RH_E_INVAL, "store aliases the bound state or workspace");
+    // step times as rh_step takes them (dt added once per step)
+    double t = *t_inout;
+    for (int k = 0; k < n_steps; ++k) {
+        char* sk = (char*)store + 3 * sb * (size_t)k;
+        const hipError_t e = hipMemcpyAsync(sk, p->state, sb, hipMemcpyDeviceToDevice, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        st = is_fp32(p) ? step_impl<float>(p, dt, 1, t, (float*)(sk + sb))
+                        : step_impl<double>(p, dt, 1, t, (double*)(sk + sb));
+        if (st != RH_OK) return st;
+        t += dt;
+    }
+    *t_inout += n_steps * dt;
+    return RH_OK;
 }
 
 rh_status rh_step_vjp_stored(rh_plan* p, double t, double dt, const void* u_n, const void* stages,

@@ -76,6 +76,7 @@ def library():
         L.rh_apply_L.argtypes = [vp, d, vp]
         L.rh_step.argtypes = [vp, d, i, dp]
         L.rh_totals.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.rh_totals_integrated.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         L.rh_reset_counters.argtypes = [vp]
         L.rh_set_timing.argtypes = [vp, i]
         L.rh_kernel_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), i]
@@ -84,6 +85,7 @@ def library():
         L.rh_vjp_workspace_bytes.restype = ctypes.c_size_t
         L.rh_step_vjp.argtypes = [vp, d, d, vp, vp, vp, vp]
         L.rh_step_store.argtypes = [vp, d, ctypes.POINTER(d), vp]
+        L.rh_step_store_n.argtypes = [vp, d, i, ctypes.POINTER(d), vp]
         L.rh_set_graph.argtypes = [vp, i]
         L.rh_step_vjp_stored.argtypes = [vp, d, d, vp, vp, vp, vp, vp]
         llp = ctypes.POINTER(ctypes.c_longlong)
@@ -101,6 +103,7 @@ def library():
         L.rh_batch_get_fields.argtypes = [vp, vp, i]
         L.rh_batch_step.argtypes = [vp, d, i, dp]
         L.rh_batch_totals.argtypes = [vp, dp, llp]
+        L.rh_batch_totals_integrated.argtypes = [vp, dp, llp]
         L.rh_batch_set_graph.argtypes = [vp, i]
         L.rh_batch_set_tuning.argtypes = [vp, i, i, i]
         L.rh_batch_get_tuning.argtypes = [vp, ip, ip, ip]
@@ -182,6 +185,13 @@ def rh_totals(plan):
     return list(out), list(cnt)
 
 
+def rh_totals_integrated(plan):
+    out = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_longlong * 2)()
+    _check(library().rh_totals_integrated(plan, out, cnt))
+    return list(out), list(cnt)
+
+
 def rh_totals_noalloc(state_ptr, precision, ncell, out_ptr, stream_ptr):
     """Enqueue the FP64 totals of a state [5][ncell] into the device buffer out_ptr[6]."""
     _check(library().rh_totals_noalloc(state_ptr, precision, ncell, out_ptr, stream_ptr))
@@ -224,6 +234,13 @@ def rh_set_graph(plan, enable):
 def rh_step_store(plan, dt, t, stages_ptr):
     tt = ctypes.c_double(t)
     _check(library().rh_step_store(plan, float(dt), ctypes.byref(tt), ctypes.c_void_p(stages_ptr)))
+    return tt.value
+
+
+def rh_step_store_n(plan, dt, n_steps, t, store_ptr):
+    tt = ctypes.c_double(t)
+    _check(library().rh_step_store_n(plan, float(dt), int(n_steps), ctypes.byref(tt),
+                                     ctypes.c_void_p(store_ptr)))
     return tt.value
 
 
@@ -335,8 +352,10 @@ class Hydro:
         self.t = rh_step(self.plan, dt, n_steps, self.t)
         return self.t
 
-    def totals(self):
-        return rh_totals(self.plan)
+    def totals(self, integrated=False):
+        """FP64 sums of the conserved fields and the counters; with integrated,
+        the sums times the cell volume."""
+        return rh_totals_integrated(self.plan) if integrated else rh_totals(self.plan)
 
     def _dev(self, a):
         t = self.torch.as_tensor(a)
@@ -366,6 +385,14 @@ class Hydro:
             stages = self.torch.empty((2,) + tuple(self.state.shape), dtype=self.dtype, device=self.device)
         self.t = rh_step_store(self.plan, dt, self.t, stages.data_ptr())
         return stages
+
+    def step_store_n(self, dt, n_steps, store=None):
+        """n_steps steps keeping (u_k, u1_k, u2_k) of each ([n][3][5][nz][ny][nx])."""
+        if store is None:
+            store = self.torch.empty((n_steps, 3) + tuple(self.state.shape), dtype=self.dtype,
+                                     device=self.device)
+        self.t = rh_step_store_n(self.plan, dt, n_steps, self.t, store.data_ptr())
+        return store
 
     def step_vjp_stored(self, u_n, stages, ubar, dt, t=None):
         """Adjoint of one SSP-RK3 step from u_n whose stage states are given."""
@@ -442,6 +469,13 @@ def rh_batch_totals(batch, n_grids):
     out = (ctypes.c_double * (5 * n_grids))()
     cnt = (ctypes.c_longlong * 2)()
     _check(library().rh_batch_totals(batch, out, cnt))
+    return [list(out[5 * g:5 * g + 5]) for g in range(n_grids)], list(cnt)
+
+
+def rh_batch_totals_integrated(batch, n_grids):
+    out = (ctypes.c_double * (5 * n_grids))()
+    cnt = (ctypes.c_longlong * 2)()
+    _check(library().rh_batch_totals_integrated(batch, out, cnt))
     return [list(out[5 * g:5 * g + 5]) for g in range(n_grids)], list(cnt)
 
 
@@ -606,7 +640,9 @@ class Batch:
         self.t = rh_batch_step(self.batch, dt, n_steps, self.t)
         return self.t
 
-    def totals(self):
+    def totals(self, integrated=False):
+        if integrated:
+            return rh_batch_totals_integrated(self.batch, self.n)
         return rh_batch_totals(self.batch, self.n)
 
     def tuning_key(self):

@@ -175,3 +175,60 @@ def test_stored_adjoint_rejects_aliasing():
         rh.rh_step_store(h.plan, spec["dt"], 0.0, h.workspace.data_ptr())
     assert e.value.status == rh.RH_E_INVAL
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["hubble", "hotspots"])
+def test_store_n_steps_and_their_adjoint(case, precision):
+    """rh_step_store_n over three steps: the final state and time are those of
+    rh_step(3) (bitwise; the step graph replays are bitwise the eager steps), the
+    store holds each step's start state and the stage states rh_step_store gives
+    from it, and the adjoint chained backward through the stored steps equals the
+    chain of recomputing adjoints bitwise."""
+    rh = rh_module()
+    import torch
+    prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
+    spec = CASES[case](5)
+    dt, t0, n = spec["dt"], spec["t0"], 3
+    h, u, w = _setup(rh, spec, prec)
+    h.set_primitive(spec["prim"])
+    u0 = h.state.clone()
+    store = h.step_store_n(dt, n)
+    final, t_end = h.state.clone(), h.t
+    h.state.copy_(u0)
+    h.t = t0
+    h.step(dt, n)
+    assert torch.equal(h.state, final) and h.t == t_end
+    h.state.copy_(u0)
+    h.t = t0
+    times = []
+    for k in range(n):
+        times.append(h.t)
+        assert torch.equal(store[k, 0], h.state)
+        stages = h.step_store(dt)
+        assert torch.equal(store[k, 1:], stages)
+    wd = torch.tensor(w, dtype=h.dtype, device="cuda")
+    a, b = wd.clone(), wd.clone()
+    for k in reversed(range(n)):
+        a = h.step_vjp_stored(store[k, 0], store[k, 1:], a, dt, t=times[k])
+        b = h.step_vjp(store[k, 0].clone(), b, dt, t=times[k])
+    assert torch.equal(a, b) and bool(torch.isfinite(a).all())
+    h.close()
+
+
+def test_store_n_rejects_bad_arguments():
+    rh = rh_module()
+    import torch
+    spec = CASES["tiny_periodic"](5)
+    h, u, w = _setup(rh, spec, rh.RH_PREC_FP64)
+    store = torch.empty((2, 3) + tuple(h.state.shape), dtype=h.dtype, device="cuda")
+    for bad in (dict(n=-1, ptr=store.data_ptr()), dict(n=1, ptr=0), dict(n=1, ptr=h.state.data_ptr()),
+                dict(n=1, ptr=h.workspace.data_ptr())):
+        with pytest.raises(rh.RHError) as e:
+            rh.rh_step_store_n(h.plan, spec["dt"], bad["n"], 0.0, bad["ptr"])
+        assert e.value.status == rh.RH_E_INVAL
+    with pytest.raises(rh.RHError) as e:
+        rh.rh_step_store_n(h.plan, 0.0, 1, 0.0, store.data_ptr())
+    assert e.value.status == rh.RH_E_INVAL
+    assert rh.rh_step_store_n(h.plan, spec["dt"], 0, 1.5, store.data_ptr()) == 1.5
+    h.close()

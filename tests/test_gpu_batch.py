@@ -232,3 +232,20 @@ def test_autotune_cache_reused(tmp_path):
     assert out[0][0] == out[1][0]
     for a, c in zip(out[0][1], out[1][1]):
         assert np.array_equal(a, c)
+
+
+def test_batch_integrals_scale_each_grid_by_its_cell_volume():
+    rh = rh_module()
+    specs = [inputs.random_smooth((16, 16, 16), h=0.1, seed=21), inputs.random_smooth((12, 20, 8), h=0.07, seed=22)]
+    b = rh.Batch(specs, precision=rh.RH_PREC_FP64)
+    b.set_primitive([sp["prim"] for sp in specs])
+    tot, cnt = b.totals()
+    integ, cnt2 = b.totals(integrated=True)
+    b.close()
+    assert cnt2 == cnt
+    for g, sp in enumerate(specs):
+        vol = float(np.prod(sp["h"]))
+        assert integ[g] == [x * vol for x in tot[g]], g
+        ref = oracle.totals(oracle.grid_from_spec(sp), oracle.prim2con(sp["prim"])) * vol
+        scale = np.abs(oracle.prim2con(sp["prim"])).reshape(5, -1).sum(1) * vol
+        assert np.all(np.abs(np.array(integ[g]) - ref) <= 1e-14 * scale), g

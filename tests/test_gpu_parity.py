@@ -110,6 +110,10 @@ def test_totals_match_oracle():
     h.step(spec["dt"], 5)
     tot2, _ = h.totals()
     assert np.all(np.abs(np.array(tot2) - ref) <= 1e-13 * scale)
+    # the integrals: the same sums times the cell volume
+    vol = float(np.prod(spec["h"]))
+    integ, cnt2 = h.totals(integrated=True)
+    assert integ == [x * vol for x in tot2] and cnt2 == cnt
     h.close()
 
 
