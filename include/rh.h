@@ -337,7 +337,7 @@ rh_status rh_step_store(rh_plan* plan, double dt, double* t_inout, void* stages)
  * rh_step_vjp_stored(plan, t_k, dt, store_k, store_k + one state, ...) with t_k
  * the time of step k as rh_step takes it (*t_inout on entry with dt added k
  * times).  *t_inout advances by n_steps * dt, as in rh_step; n_steps == 0 is a
- * no-op.  Asynchronous on the bound stream (the steps run eagerly, not from the
+ * no-op (store may then be NULL).  Asynchronous on the bound stream (the steps run eagerly, not from the
  * step graph; a failed call leaves the steps before it done and *t_inout
  * unchanged).  Errors: RH_E_STATE (unbound), RH_E_INVAL (NULL, dt <= 0,
  * n_steps < 0, store aliasing the bound state or workspace). */

@@ -1603,7 +1603,7 @@ rh_status rh_step_store_n(rh_plan* p, double dt, int n_steps, double* t_inout, v
     TraceRange trace("rh_step_store_n");
     rh_status st = check_bound(p);
     if (st != RH_OK) return st;
-    if (!t_inout || !store) return fail(RH_E_INVAL, "NULL argument");
+    if (!t_inout || (!store && n_steps != 0)) return fail(RH_E_INVAL, "NULL argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
     if (n_steps < 0) return fail(RH_E_INVAL, "n_steps must be >= 0");
     const size_t sb = rh_state_bytes(p);

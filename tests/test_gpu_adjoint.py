@@ -231,4 +231,5 @@ def test_store_n_rejects_bad_arguments():
         rh.rh_step_store_n(h.plan, 0.0, 1, 0.0, store.data_ptr())
     assert e.value.status == rh.RH_E_INVAL
     assert rh.rh_step_store_n(h.plan, spec["dt"], 0, 1.5, store.data_ptr()) == 1.5
+    assert rh.rh_step_store_n(h.plan, spec["dt"], 0, 1.5, 0) == 1.5
     h.close()
