@@ -1607,6 +1607,7 @@ rh_status rh_step_store_n(rh_plan* p, double dt, int n_steps, double* t_inout, v
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RH_E_INVAL, "dt must be > 0");
     if (n_steps < 0) return fail(RH_E_INVAL, "n_steps must be >= 0");
     const size_t sb = rh_state_bytes(p);
+    if (n_steps > 0 && (size_t)n_steps > SIZE_MAX / (3 * sb)) return fail(RH_E_INVAL, "store size overflows");
     const size_t total = 3 * sb * (size_t)n_steps;
     if (n_steps > 0 && (overlaps(store, total, p->state, sb) || overlaps(store, total, p->ws, 3 * sb)))
         return fail(RH_E_INVAL, "store aliases the bound state or workspace");
