@@ -105,3 +105,36 @@ def test_library_calls_carry_roctx_ranges(lib):
     src = open(os.path.join(ROOT, "paper_1604_03360_amd", "csrc", "rh_api.hip")).read()
     for name in ("rh_step", "rh_apply_L", "rh_batch_step", "rh_apply_vjp", "rh_step_vjp"):
         assert 'TraceRange trace("%s")' % name in src
+
+
+def test_plain_c_program_links_and_calls_the_library(lib, tmp_path):
+    """The boundary is a C ABI: a C99 program includes rh.h, links librh.so and
+    gets a clean error for an invalid description without a GPU."""
+    import shutil
+    import subprocess
+    from paper_1604_03360_amd import rh
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_rh.c"
+    src.write_text(
+        '#include "rh.h"\n'
+        '#include <stdio.h>\n'
+        '#include <string.h>\n'
+        'int main(void) {\n'
+        '    rh_grid_desc d;\n'
+        '    rh_plan* p = NULL;\n'
+        '    memset(&d, 0, sizeof(d));   /* nx = 0: invalid */\n'
+        '    rh_status st = rh_plan_create(&p, &d);\n'
+        '    printf("%s|%d|%s\\n", rh_version(), (int)st, rh_last_error());\n'
+        '    return (st == RH_E_INVAL && p == NULL) ? 0 : 1;\n'
+        '}\n')
+    exe = tmp_path / "use_rh"
+    libdir = os.path.dirname(rh.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", str(src), "-I",
+                    os.path.join(ROOT, "include"), "-L", libdir, "-l:librh.so", "-Wl,-rpath," + libdir,
+                    "-o", str(exe)], check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stdout + out.stderr
+    version, status, message = out.stdout.strip().split("|", 2)
+    assert version and int(status) == rh.RH_E_INVAL and message
