@@ -329,6 +329,34 @@ def test_ideal_gas_batch_equals_single_grids(precision):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ideal_gas_shock_tube_full_run_against_exact_solution(precision):
+    """The gamma = 5/3 shock tube to t = 0.4 on 800 cells (WENO5, local
+    splitting) on the GPU against the exact solution of tests/ideal_riemann.py:
+    the same L1 bars as the oracle's own run (n 0.06, p 0.045, v 0.006) and the
+    star plateau within 0.5%."""
+    import ideal_riemann as ir
+    rh = rh_module()
+    prec = rh.RH_PREC_FP64 if precision == "fp64" else rh.RH_PREC_FP32
+    gam = 5.0 / 3.0
+    pL, pR = (gam - 1.0) * (29.995 - 10.0), (gam - 1.0) * (1.0000015 - 1.0)
+    spec = inputs.with_scheme(inputs.sod_ideal(nx=800), order=5, lf_local=True)
+    h = _hydro(rh, spec, prec)
+    t = h.step(spec["dt"], spec["nsteps"])
+    prim = h.get(rh.RH_FIELDS_PRIMITIVE).reshape(5, 800)
+    h.close()
+    x = spec["c0"][0] + spec["h"][0] * np.arange(800)
+    ex = ir.sample(10.0, pL, 1.0, pR, gam, x / t)
+    got = np.array([prim[4], (gam - 1.0) * (prim[0] - prim[4]), prim[1]])
+    err = np.abs(got - ex).sum(axis=1) * spec["h"][0]
+    s = ir.star_state(10.0, pL, 1.0, pR, gam)
+    i = np.argmin(np.abs(x - 0.5 * (s["xi_tail"] + s["v"]) * t))
+    print("ideal tube exact", precision, err, got[1, i] / s["p"] - 1.0, flush=True)
+    assert t == pytest.approx(0.4, abs=1e-12)
+    assert np.all(err < [0.06, 0.045, 0.006]), err
+    assert got[1, i] == pytest.approx(s["p"], rel=5e-3) and got[2, i] == pytest.approx(s["v"], rel=5e-3)
+
+
 # ---------------------------------------------------------------------------
 # Paths and errors
 # ---------------------------------------------------------------------------
