@@ -513,7 +513,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--scheme", type=int, default=5, choices=(5, 7))
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=5,
+                    help="whole-grid oracle steps timed for cpu_baseline (about 12 s on 16 host cores)")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="timed steps of the 64-event ensemble (its configured run length)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
