@@ -294,7 +294,7 @@ rh_status evaluate(rh_plan* p, const T* us, const T* u0, T* lacc, T* uout, doubl
         }, "stage launch");
     }
     int i0 = 0;
-    if (na >= 2 && active[0] == 0 && active[1] == 1 && rh::sweep_xy_applies(p->d.scheme, sizeof(T) == 4, n, p->d.bc[0])) {
+    if (na >= 2 && active[0] == 0 && active[1] == 1 && rh::sweep_xy_applies(p->d.scheme, n, p->d.bc[0])) {
         // x and y in one launch
         rh::SweepArgs<T> b = a;
         b.first = 1;

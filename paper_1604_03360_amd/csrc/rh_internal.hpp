@@ -133,10 +133,9 @@ int choose_tile_x(int nx, int ghosts);
 int choose_segment(int n, int ncols);
 
 // Fused x and y sweeps (one launch doing both axes, bitwise the result of the
-// x sweep followed by the y sweep): applies to WENO5 grids and FP32 WENO7 grids
-// with a periodic x axis of 64, 128, 192 or 256 cells and more than one cell
-// along y.
-bool sweep_xy_applies(int order, bool fp32, const int n[3], int bc_x);
+// x sweep followed by the y sweep): applies to WENO5 and WENO7 grids with a
+// periodic x axis of 64, 128, 192 or 256 cells and more than one cell along y.
+bool sweep_xy_applies(int order, const int n[3], int bc_x);
 // a: the y sweep's arguments (first = 1; bc, inv_h of y); inv_hx = 1 / dx.
 template <class T>
 hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s);

@@ -650,7 +650,7 @@ static hipError_t launch_roll(SweepArgs<T> a, hipStream_t s) {
 template <class T, int ORDER>
 __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_xy(SweepArgs<T> A, T inv_hx) {
     constexpr int R = (ORDER + 1) / 2, W = 2 * R;
-    constexpr int D = R + 1;              // rows whose x part of L is pending
+    constexpr int D = R;                  // rows whose x part of L is pending (row k's slot is read before row k + R enters)
     __shared__ T sx[2][5][256 + 2 * R];   // x split fluxes of the current row, halo copies at both ends
     __shared__ T sF[5][256];              // x face fluxes F(x + 1/2) of the current row
     __shared__ T lxr[D][5][256];          // x part of L of the last rows, by row mod D (rows are
@@ -741,6 +741,9 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
         for (int f = 0; f < 5; ++f) u[f] = nxt[f];
         fetch(k + 1 + R, nxt);
         const uint32_t off = cb + (uint32_t)k * sb;
+        T lxk[5];   // x part of L of row k, read before row k + R takes its slot
+#pragma unroll
+        for (int c = 0; c < 5; ++c) lxk[c] = lxr[k % D][c][x];
         T fp[5], fm[5];
         enter(k + R, u, fp, fm);
 #pragma unroll
@@ -753,13 +756,12 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
             wp[c][W - 1] = fp[c];
             wm[c][W - 1] = fm[c];
         }
-        const int slot = k % D;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             const T Fr = recon_plus<T, ORDER>(wp[c], eps2) + recon_minus<T, ORDER>(wm[c], eps2);
             const T Lk = (Fl[c] - Fr) * hinv;
             Fl[c] = Fr;
-            const T L = lxr[slot][c][x] + Lk;
+            const T L = lxk[c] + Lk;
             T v;
             if (A.stage == STAGE_WRITE_L) {
                 v = L;
@@ -776,18 +778,18 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
 
 // RH_FUSE_XY=0 in the environment selects the separate sweeps everywhere (the
 // results are bitwise the same; used to compare the two paths).
-bool sweep_xy_applies(int order, bool fp32, const int n[3], int bc_x) {
+bool sweep_xy_applies(int order, const int n[3], int bc_x) {
     static const bool off = [] {
         const char* e = getenv("RH_FUSE_XY");
         return e && e[0] == '0';
     }();
-    return !off && (order == 5 || (order == 7 && fp32)) && bc_x == RH_BC_PERIODIC && n[0] % 64 == 0 &&
+    return !off && (order == 5 || order == 7) && bc_x == RH_BC_PERIODIC && n[0] % 64 == 0 &&
            n[0] >= 64 && n[0] <= 256 && n[1] > 1;
 }
 
 template <class T>
 hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s) {
-    if (!(order == 5 || (order == 7 && sizeof(T) == 4)) || a.n[0] % 64 != 0 || a.n[0] < 64 || a.n[0] > 256)
+    if (!(order == 5 || order == 7) || a.n[0] % 64 != 0 || a.n[0] < 64 || a.n[0] > 256)
         return hipErrorInvalidValue;
     const int seg = choose_segment(a.n[1], a.n[0] * a.n[2]);
     a.seg = seg;
@@ -795,8 +797,7 @@ hipError_t launch_sweep_xy(int order, SweepArgs<T> a, T inv_hx, hipStream_t s) {
     const dim3 grid((unsigned)a.n[2], gy), block((unsigned)a.n[0]);
     if (order == 5) {
         sweep_xy<T, 5><<<grid, block, 0, s>>>(a, inv_hx);
-    } else if constexpr (sizeof(T) == 4) {
-        // FP64 WENO7 would need 82 KB of LDS per block (one block per CU): split sweeps
+    } else {
         sweep_xy<T, 7><<<grid, block, 0, s>>>(a, inv_hx);
     }
     return hipGetLastError();
