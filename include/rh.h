@@ -230,10 +230,13 @@ rh_status rh_totals(rh_plan* plan, double out[5], long long counters[2]);
  * synchronisation and errors as rh_totals (on RH_E_PHYS out is still filled). */
 rh_status rh_totals_integrated(rh_plan* plan, double out[5], long long counters[2]);
 
-/* Replay steps from a graph (enable != 0): rh_step then captures one SSP-RK3
- * step (its sweep launches, Sec. 1) into a hipGraph on first use and launches
- * that graph once per step; the graph is rebuilt when dt or the bound buffers
- * change.  Results are bitwise those of eager launches.  Plans with an analytic
+/* Replay steps from graphs (enable != 0): rh_step then captures one SSP-RK3
+ * step (its sweep launches, Sec. 1) into a hipGraph on first use, and four
+ * steps into another once a call asks for at least four; a call replays the
+ * four-step graph while four or more steps remain and the one-step graph for
+ * the rest (one graph launch per four steps saves the idle time between
+ * launches).  The graphs are rebuilt when dt or the bound buffers change.
+ * Results are bitwise those of eager launches.  Plans with an analytic
  * boundary, and steps taken while per-launch timing is on, run eagerly.
  * Errors: RH_E_INVAL (NULL plan). */
 rh_status rh_set_graph(rh_plan* plan, int enable);

@@ -105,6 +105,8 @@ struct rh_plan {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph_n = nullptr;           // kGraphSteps steps in one graph
+    hipGraphExec_t graph_exec_n = nullptr;
     double graph_dt = 0.0;
     const void* graph_state = nullptr;
     const void* graph_ws = nullptr;
@@ -349,13 +351,48 @@ rh_status one_step(rh_plan* p, double dt, double t, T* stages) {
 void drop_graph(rh_plan* p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->graph_exec_n) (void)hipGraphExecDestroy(p->graph_exec_n);
+    if (p->graph_n) (void)hipGraphDestroy(p->graph_n);
     p->graph_exec = nullptr;
     p->graph = nullptr;
+    p->graph_exec_n = nullptr;
+    p->graph_n = nullptr;
 }
 
-// n steps: eager launches, or replays of one captured step when graphs are on
-// (not with analytic boundaries, whose stage times change every step, and not
-// while per-launch timing is on)
+// Steps per replay of the multi-step graph: a graph launch boundary costs about
+// 10 us of idle GPU between the last kernel of one replay and the first of the
+// next, which a graph of several steps pays once.
+constexpr int kGraphSteps = 4;
+
+// Capture `count` steps of size dt into *graph and instantiate them in *exec.
+template <class T>
+rh_status capture_steps(rh_plan* p, double dt, double t, int count, hipGraph_t* graph, hipGraphExec_t* exec) {
+    hipError_t e;
+    if (!p->cap_stream && (e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    hipStream_t keep = p->stream;
+    p->stream = p->cap_stream;
+    rh_status st = RH_OK;
+    for (int k = 0; k < count && st == RH_OK; ++k) st = one_step<T>(p, dt, t + k * dt, nullptr);
+    p->stream = keep;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != RH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    *graph = g;
+    if ((e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return RH_OK;
+}
+
+// n steps: eager launches, or replays of captured steps when graphs are on
+// (kGraphSteps steps per replay while at least that many remain, then single
+// steps; not with analytic boundaries, whose stage times change every step,
+// and not while per-launch timing is on)
 template <class T>
 rh_status step_impl(rh_plan* p, double dt, int nsteps, double t, T* stages = nullptr) {
     const bool use_graph = p->graph_on && !stages && !any_hubble(p) && !p->timing;
@@ -370,33 +407,28 @@ rh_status step_impl(rh_plan* p, double dt, int nsteps, double t, T* stages = nul
     if (nsteps == 0) return RH_OK;
     if (!p->graph_exec || p->graph_dt != dt || p->graph_state != p->state || p->graph_ws != p->ws) {
         drop_graph(p);
-        hipError_t e;
-        if (!p->cap_stream &&
-            (e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(e, "hipStreamCreateWithFlags");
-        if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return hip_fail(e, "hipStreamBeginCapture");
-        hipStream_t keep = p->stream;
-        p->stream = p->cap_stream;
-        rh_status st = one_step<T>(p, dt, t, nullptr);
-        p->stream = keep;
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(p->cap_stream, &g);
+        rh_status st = capture_steps<T>(p, dt, t, 1, &p->graph, &p->graph_exec);
         if (st != RH_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
-        }
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        p->graph = g;
-        if ((e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
             drop_graph(p);
-            return hip_fail(e, "hipGraphInstantiate");
+            return st;
         }
         p->graph_dt = dt;
         p->graph_state = p->state;
         p->graph_ws = p->ws;
     }
-    for (int k = 0; k < nsteps; ++k) {
+    if (nsteps >= kGraphSteps && !p->graph_exec_n) {
+        rh_status st = capture_steps<T>(p, dt, t, kGraphSteps, &p->graph_n, &p->graph_exec_n);
+        if (st != RH_OK) {
+            drop_graph(p);
+            return st;
+        }
+    }
+    int k = 0;
+    for (; k + kGraphSteps <= nsteps; k += kGraphSteps) {
+        hipError_t e = hipGraphLaunch(p->graph_exec_n, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    for (; k < nsteps; ++k) {
         hipError_t e = hipGraphLaunch(p->graph_exec, p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
