@@ -137,6 +137,12 @@ def run_gpu(spec, precision, steps, warmup, path=None):
         h.step(dt, 4)
         torch.cuda.synchronize()
         settle_steps += 4
+    # back to the initial state, so that the warm-up and timed steps are the
+    # first steps of the run (the settling replays would otherwise carry the blob
+    # to the end of its 200 steps, where the recovery's velocity cap acts)
+    h.set_primitive(spec["prim"])
+    h.t = spec["t0"]
+    rh.rh_reset_counters(h.plan)
     if warmup:
         h.step(dt, warmup)
     stream = torch.cuda.current_stream()

@@ -1567,8 +1567,10 @@ rh_status step_vjp_core(rh_plan* p, double t, double dt, const T* un, const T* u
     // b1 = 1/4 b2 + 1/4 dt J(u1)^T b2
     const rh::Lin3<T> i1 = {(T)0.25, (T)0, (T)0, b2, nullptr, nullptr};
     if ((st = vjp_impl<T>(p, t + dt, u1, b2, b1, i1, (T)0.25 * td)) != RH_OK) return st;
-    // out = (1/3 b + 3/4 b2 + b1) + dt J(un)^T b1
-    const rh::Lin3<T> i0 = {(T)(1.0 / 3.0), (T)0.75, (T)1, bin, b2, b1};
+    // out = (1/3 b + 3/4 b2 + b1) + dt J(un)^T b1; the forward's last stage is
+    // u^n + c (v - u^n) with c = 2/3 rounded, so its weight on u^n is 1 - c
+    // (exact in both precisions) rather than 1/3 rounded
+    const rh::Lin3<T> i0 = {(T)1 - (T)(2.0 / 3.0), (T)0.75, (T)1, bin, b2, b1};
     return vjp_impl<T>(p, t, un, b1, bout, i0, td);
 }
 

@@ -42,6 +42,14 @@ __device__ inline void hubble_conserved(const HubbleBC& hb, double x, double y, 
     u[4] = n * sqrt(g2);
 }
 
+// Last SSP-RK3 stage, u^n / 3 + 2/3 (u2 + dt L(u2)) with v = u2 + dt L(u2),
+// evaluated in increment form u^n + 2/3 (v - u^n).  The plain form's rounded
+// weights sum to 1 + 3e-8 in FP32, which scales every state (and the totals of
+// a periodic grid) by that factor each step; in increment form the rounding of
+// 2/3 multiplies only the increment and a uniform state stays exactly uniform.
+template <class T>
+__device__ __forceinline__ T rk3_last(T un, T v) { return un + (T)(2.0 / 3.0) * (v - un); }
+
 // Reciprocals.  FP32: the hardware reciprocal (about 1 ulp).  FP64: the
 // hardware estimate refined by two Newton-Raphson steps r <- r + r (1 - x r),
 // which carries the estimate to full double precision for the normal-range

@@ -106,7 +106,7 @@ __device__ __forceinline__ void epilogue(const SweepArgs<T>& A, long long id, T 
         const long long q = c * A.fstride + id;
         T v = A.us[q] + A.dt * L[c];
         if (A.stage == STAGE_2) v = (T)0.75 * A.u0[q] + (T)0.25 * v;
-        else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * A.u0[q] + (T)(2.0 / 3.0) * v;
+        else if (A.stage == STAGE_3) v = rk3_last(A.u0[q], v);
         A.uout[q] = v;
     }
 }
@@ -319,7 +319,7 @@ __device__ __forceinline__ void sweep_roll_body(const SweepArgs<T>& A, unsigned 
             } else {
                 v = us[c] + A.dt * L;
                 if (A.stage == STAGE_2) v = (T)0.75 * u0[c] + (T)0.25 * v;
-                else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * u0[c] + (T)(2.0 / 3.0) * v;
+                else if (A.stage == STAGE_3) v = rk3_last(u0[c], v);
             }
             st_off(A.stage == STAGE_WRITE_L ? A.lacc + c * F : A.uout + c * F, off, v);
         }
@@ -768,7 +768,7 @@ __global__ void __launch_bounds__(256, (RollMinBlocks<T, ORDER>::value)) sweep_x
             } else {
                 v = ld_off(A.us + c * F, off) + A.dt * L;
                 if (A.stage == STAGE_2) v = (T)0.75 * ld_off(A.u0 + c * F, off) + (T)0.25 * v;
-                else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * ld_off(A.u0 + c * F, off) + (T)(2.0 / 3.0) * v;
+                else if (A.stage == STAGE_3) v = rk3_last(ld_off(A.u0 + c * F, off), v);
             }
             st_off(A.stage == STAGE_WRITE_L ? A.lacc + c * F : A.uout + c * F, off, v);
         }

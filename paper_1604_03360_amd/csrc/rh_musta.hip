@@ -288,8 +288,7 @@ __global__ void __launch_bounds__(256, (MustaMinBlocks<T>::value)) stage_musta(S
                     } else {
                         v = zw[1][c] + A.dt * L;
                         if (A.stage == STAGE_2) v = (T)0.75 * ld_off(u0 + c * F, off) + (T)0.25 * v;
-                        else if (A.stage == STAGE_3)
-                            v = (T)(1.0 / 3.0) * ld_off(u0 + c * F, off) + (T)(2.0 / 3.0) * v;
+                        else if (A.stage == STAGE_3) v = rk3_last(ld_off(u0 + c * F, off), v);
                     }
                     if (act) st_off(out + c * F, off, v);
                 }

@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(256, (StageMinBlocks<T, ORDER, TX, LOCAL>::val
             } else {
                 v = usk + A.dt * L;
                 if (A.stage == STAGE_2) v = (T)0.75 * u0k + (T)0.25 * v;
-                else if (A.stage == STAGE_3) v = (T)(1.0 / 3.0) * u0k + (T)(2.0 / 3.0) * v;
+                else if (A.stage == STAGE_3) v = rk3_last(u0k, v);
             }
             if (act) st_off(out + c * F, off, v);
         }

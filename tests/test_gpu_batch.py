@@ -168,23 +168,28 @@ def test_batch_rejects_mixed_or_degenerate_grids():
 
 
 def test_full_ensemble_sampled_events():
-    """The 64-event ensemble (cubes of 64..160 cells, FP32, WENO5): two steps of
-    the batch; sampled events equal their single-grid runs bitwise and every
-    event conserves its totals to FP32 round-off."""
+    """The 64-event ensemble (cubes of 64..160 cells, FP32, WENO5) over its whole
+    run (100 steps, one launch per stage, replayed from graphs): sampled events
+    of every size equal their single-grid runs bitwise and every event conserves
+    its totals to FP32 round-off."""
     rh = rh_module()
     specs = inputs.batch()
     dt = specs[0]["dt"]
+    nsteps = specs[0]["nsteps"]
+    assert nsteps == 100
     b = rh.Batch(specs, precision=rh.RH_PREC_FP32)
     b.set_primitive([sp["prim"] for sp in specs])
     tot0, _ = b.totals()
     rh.rh_batch_set_graph(b.batch, True)
-    b.step(dt, 2)
+    b.step(dt, nsteps)
     tot1, cnt = b.totals()
     got = b.get()
     b.close()
     assert cnt[1] == 0
-    for g in (0, 7, 13, 63):
-        ref = run_single(rh, specs[g], rh.RH_PREC_FP32, 2, dt)
+    sizes = [sp["shape"][0] for sp in specs]
+    picks = sorted({0, 63} | {sizes.index(s) for s in set(sizes)})
+    for g in picks:
+        ref = run_single(rh, specs[g], rh.RH_PREC_FP32, nsteps, dt)
         assert np.array_equal(got[g], ref), g
     for g, sp in enumerate(specs):
         u0 = oracle.prim2con(sp["prim"])

@@ -8,7 +8,8 @@ times (the library's default tile and segment choice for the shape).
   oracle, FP32 against FP64, the energy density against its closed form);
 * the 64-event hot-spot ensemble advanced as one batch for ten steps: the
   smallest and the largest events against the oracle run of the same event alone;
-* the blob's full run length (200 steps) on a 64^3 variant.
+* the blob's full run length (200 steps) on a 64^3 variant against the oracle,
+  and at 256^3 against conservation, mirror symmetry and FP64 (FP32).
 
 Bars as in the small-grid parity tests: 1e-12 (FP64) and 2e-5 (FP32) normalised
 L-infinity per field (1e-5 for FP32 on the smooth Hubble-like flow).
@@ -18,7 +19,7 @@ import pytest
 
 import oracle
 from paper_1604_03360_amd import inputs
-from gpu_helpers import field_errors, gpu_steps, oracle_steps, rh_module
+from gpu_helpers import field_errors, gpu_hydro, gpu_steps, oracle_steps, rh_module
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -139,6 +140,78 @@ def test_blob_64_full_length():
     assert np.all(err64 <= 1e-12), err64
     assert np.all(err32 <= 2e-5), err32
     assert cnt == [0, 0] and cnt32[1] == 0
+
+
+def mirror(u, axis):
+    """The mirror image of a state u[5][nz][ny][nx] in spatial axis 0 (x), 1 (y)
+    or 2 (z): the cells reversed along the axis and the momentum along it negated."""
+    sign = np.ones((5, 1, 1, 1))
+    sign[1 + axis] = -1.0
+    return sign * np.flip(u, axis=3 - axis)
+
+
+def symmetrised(prim):
+    """prim made exactly even in x, y and z (each average is commutative, so the
+    result equals its mirror images bit for bit; the cell centres of the grid are
+    only symmetric to rounding)."""
+    p = np.array(prim, dtype=np.float64)
+    for axis in range(3):
+        p = 0.5 * (p + np.flip(p, axis=3 - axis))
+    return p
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_blob_256_full_length(order, blob_specs):
+    """The blob at full size over its whole run (200 steps to t = 8), stepped as the
+    benchmark steps it (graph replays).  The oracle cannot take 200 steps at
+    256^3, so the run is held to what holds at any size:
+
+    * mirror symmetry, bit for bit: every operation of the scheme commutes with
+      negation, so from initial data that are exactly even in x, y and z every
+      later state equals its three mirror images exactly (with the momentum
+      along the mirrored axis odd), in FP64 and FP32, floors included;
+    * conservation of the totals of E, M and N to round-off (periodic grid),
+      which after 200 steps is about 5e-8 (FP32) and 1e-16 (FP64) of the totals;
+    * FP32 within the smooth-flow bar (1e-5 per field) of FP64 after 100 steps.
+
+    From about step 130 the expanding shell meets its periodic images and leaves
+    a near-vacuum interior (E down to about 5e-14) where the velocity cap of the
+    recovery acts: no floor before step 100, none non-finite at any time, and
+    FP32 no longer tracks FP64 to that bar there (the flow is ill-conditioned)."""
+    rh = rh_module()
+    spec = dict(blob_specs[order])
+    spec["prim"] = symmetrised(spec["prim"])
+    for axis in range(3):
+        assert np.array_equal(spec["prim"], mirror(spec["prim"], axis))
+    nsteps = spec["nsteps"]
+    assert nsteps == 200
+    scale = np.abs(oracle.prim2con(spec["prim"])).reshape(5, -1).sum(1).max()  # momenta start at 0
+    half = {}
+    for name, prec in (("fp64", rh.RH_PREC_FP64), ("fp32", rh.RH_PREC_FP32)):
+        h = gpu_hydro(spec, prec)
+        tot0, _ = h.totals()
+        rh.rh_set_graph(h.plan, 1)
+        for k in (nsteps // 2, nsteps):
+            print("blob 256^3 WENO%d %s, to step %d" % (order, name, k), flush=True)
+            h.step(spec["dt"], nsteps // 2)
+            tot, cnt = h.totals()
+            u = h.get()
+            drift = np.abs(np.array(tot) - np.array(tot0)) / scale
+            print(name, "step", k, "totals drift", drift, "counters", cnt, flush=True)
+            assert cnt[1] == 0 and np.all(np.isfinite(u))
+            for axis in range(3):
+                assert np.array_equal(u, mirror(u, axis)), (name, k, axis)
+            # FP32: round-off of 200 steps of cell updates is below 1e-7 of the totals
+            # (a last-stage combine whose rounded weights do not sum to one drifts
+            # by 2e-6 per 100 steps)
+            assert np.all(drift <= (1e-12 if name == "fp64" else 2e-7)), drift
+            if k == nsteps // 2:
+                assert cnt[0] == 0
+                half[name] = u
+        h.close()
+    err32 = field_errors(half["fp32"], half["fp64"])
+    print("fp32 vs fp64 after %d steps" % (nsteps // 2), err32, flush=True)
+    assert np.all(err32 <= 1e-5), err32
 
 
 def test_blob_256_adjoint_against_oracle(blob_specs, blob_oracle):
