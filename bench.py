@@ -276,18 +276,26 @@ def run_diff(n_steps=50, every=10):
 
 def run_batch(steps, warmup):
     """The 64-event hot-spot ensemble (FP32, WENO5): autotuned launch shapes,
-    graph-captured steps; events resident in HBM before the timed region."""
+    graph-captured steps; after the warm-up steps the events are reset to their
+    initial state, resident in HBM, so that the timed steps are the ensemble's
+    run (100 steps by default)."""
     import torch
     from paper_1604_03360_amd import inputs, rh
     specs = inputs.batch()
+    prims = [sp["prim"] for sp in specs]
     b = rh.Batch(specs, precision=rh.RH_PREC_FP32)
-    b.set_primitive([sp["prim"] for sp in specs])
+    b.set_primitive(prims)
     ncell = sum(sp["shape"][0] * sp["shape"][1] * sp["shape"][2] for sp in specs)
+    t0 = specs[0]["t0"]
     del specs
     tuning = rh.rh_batch_autotune(b.batch, 2)
     rh.rh_batch_set_graph(b.batch, True)
     dt = inputs.CFL * 0.15
     b.step(dt, warmup)
+    # the timed steps are the ensemble's run from its initial state
+    b.set_primitive(prims)
+    b.t = t0
+    del prims
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
