@@ -205,8 +205,10 @@ rh_status rh_apply_L(rh_plan* plan, double t, void* L_out);
 
 /* Advance the bound state by n_steps steps of the Shu-Osher SSP-RK3 method
  * (Sec. 1): u1 = u + dt L(u, t); u2 = 3/4 u + 1/4 (u1 + dt L(u1, t+dt));
- * u <- 1/3 u + 2/3 (u2 + dt L(u2, t+dt/2)).  The combine of each stage is
- * fused into its last directional sweep.  *t_inout is the physical time of the
+ * u <- 1/3 u + 2/3 (u2 + dt L(u2, t+dt/2)), the last stage evaluated as
+ * u + c (v - u) with v = u2 + dt L(u2) and c = 2/3 in the plan precision.  The
+ * combine of each stage is fused into its last directional sweep (or into the
+ * stage kernel).  *t_inout is the physical time of the
  * state (used for HUBBLE boundaries) and is advanced by n_steps*dt on return
  * (host-side; the device work is asynchronous).  n_steps == 0 is a no-op.
  * Errors: RH_E_INVAL (dt <= 0, n_steps < 0, NULL t_inout), RH_E_STATE, RH_E_HIP. */
@@ -319,7 +321,8 @@ size_t rh_vjp_workspace_bytes(const rh_plan* plan);
  * recomputed into scratch (rh_vjp_workspace_bytes), then
  *   b2 = 2/3 b + 2/3 dt J(u2)^T b,  b1 = 1/4 b2 + 1/4 dt J(u1)^T b2,
  *   ubar_out = 1/3 b + 3/4 b2 + b1 + dt J(u_n)^T b1   (b = ubar_in),
- * with J(u2) at t + dt/2, J(u1) at t + dt, J(u_n) at t.  The plan must be bound;
+ * with J(u2) at t + dt/2, J(u1) at t + dt, J(u_n) at t; the weights 2/3 and
+ * 1/3 are c and 1 - c of the forward's last stage.  The plan must be bound;
  * its workspace is overwritten (recomputation and recovery pack) and may
  * not alias any operand.  ubar_out may alias ubar_in.  Errors: RH_E_STATE
  * (unbound), RH_E_INVAL. */
