@@ -70,6 +70,25 @@ def hubble(n=128, order=5, t0=10.0, half_width=5.0, nsteps=100, e0=1.0, n0=0.5, 
                  order=order, t0=t0, nsteps=nsteps, hub=(t0, e0, n0))
 
 
+def ellipsoidal(n=128, order=5, t0=10.0, half_width=5.0, nsteps=100, e0=1.0, n0=0.5, n1=1.0,
+                axes=(0.03, 0.04, 0.05), shape=None):
+    """Hubble-like flow carrying an ellipsoidal charge: e and v as in hubble(), and
+    n = (t0/tau)^3 (n0 + n1 exp(-s/2)), s = (x^2/a^2 + y^2/b^2 + z^2/c^2) / t^2 at
+    t = t0, with (a, b, c) = axes (speeds: the ellipsoid's semi-axes grow as a t)."""
+    spec = hubble(n=n, order=order, t0=t0, half_width=half_width, nsteps=nsteps, e0=e0, n0=n0,
+                  shape=shape)
+    nx, ny, nz = spec["shape"]
+    h, c0 = spec["h"][0], spec["c0"][0]
+    Z, Y, X = np.meshgrid(_centres(nz, h, c0), _centres(ny, h, c0), _centres(nx, h, c0), indexing="ij")
+    a, b, c = axes
+    tau = np.sqrt(t0 * t0 - (X * X + Y * Y + Z * Z))
+    s = (X * X / (a * a) + Y * Y / (b * b) + Z * Z / (c * c)) / (t0 * t0)
+    spec["prim"][4] = (t0 / tau) ** 3 * (n0 + n1 * np.exp(-0.5 * s))
+    spec["name"] = "ellipsoidal"
+    spec["ellipsoid"] = (float(n1), float(a), float(b), float(c))
+    return spec
+
+
 def _centred_axis(n, h):
     return _centres(n, h, -(0.5 * n - 0.5) * h)
 

@@ -462,6 +462,31 @@ def test_hubble_run_accuracy(orc):
     assert errs[(7, 32)] < errs[(5, 32)]
 
 
+def test_ellipsoidal_charge_L_truncation_order(orc):
+    """Exact ellipsoidal flow (the Hubble-like flow carrying an ellipsoidal
+    charge, see tests/ellipsoidal_exact.py) with analytic boundary cells: the
+    charge component of L(u_exact) approaches dN_exact/dt at close to the design
+    order on [-3, 3]^3 at t = 10, where the charge profile is 3 to 9 cells per
+    semi-axis (64^3 -> 128^3: 4.45 for WENO5, 5.71 for WENO7); the ghost cells,
+    which carry the uniform background charge only, miss less than 1e-12."""
+    import ellipsoidal_exact as ex
+    for order, expect in ((5, 4.0), (7, 5.2)):
+        errs = []
+        for n in (64, 128):
+            spec = inputs.ellipsoidal(n=n, order=order, half_width=3.0, axes=(0.03, 0.035, 0.04))
+            assert ex.ghost_mismatch(spec, spec["t0"], 4) < 1e-12
+            g = orc.grid_from_spec(spec)
+            u = orc.prim2con(spec["prim"])
+            L = orc.apply_L(g, u, t=spec["t0"])
+            xyz = ex.cell_centres(spec)
+            at = lambda t: orc.prim2con(ex.primitives(spec, t, xyz))
+            dt = 1e-3
+            t0 = spec["t0"]
+            dudt = (8 * (at(t0 + dt) - at(t0 - dt)) - (at(t0 + 2 * dt) - at(t0 - 2 * dt))) / (12 * dt)
+            errs.append(np.abs(L[4] - dudt[4]).max())
+        assert np.log2(errs[0] / errs[1]) > expect, errs
+
+
 def test_hubble_stage_times(orc):
     """Boundary values evaluated at the right stage times keep the Hubble run
     third order in time (wrong stage times would leave an O(dt) error)."""
