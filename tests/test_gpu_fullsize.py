@@ -128,7 +128,8 @@ def test_hubble_128_full_run_against_analytic():
 
 def test_blob_64_full_length():
     """The blob's full run length (200 steps of dt = 0.04 to t = 8) on a 64^3 variant
-    (dx = 0.1, periodic): FP64 against the oracle step for step, FP32 against FP64."""
+    (dx = 0.1, periodic): FP64 against the oracle step for step, FP32 against FP64
+    within the smooth-flow FP32 bar, 1e-5 per field (measured 1.2-2.0e-6)."""
     rh = rh_module()
     spec = inputs.blob(n=64, order=5)
     g64, _, tot, cnt = gpu_steps(spec, rh.RH_PREC_FP64, 200)
@@ -138,7 +139,7 @@ def test_blob_64_full_length():
     err32 = field_errors(g32, g64)
     print("blob 64^3 x 200: fp64 vs oracle", err64, "fp32 vs fp64", err32, flush=True)
     assert np.all(err64 <= 1e-12), err64
-    assert np.all(err32 <= 2e-5), err32
+    assert np.all(err32 <= 1e-5), err32
     assert cnt == [0, 0] and cnt32[1] == 0
 
 
