@@ -414,7 +414,33 @@ def hubble_field_errors(n=128, nsteps=100):
     return out
 
 
-def roofline(run, precision, order, ncell):
+def copy_rate(nbytes=1 << 30, reps=20):
+    """Rate (GB/s, bytes read plus bytes written) of a plain device-to-device copy
+    of 1 GiB, timed with events after the same clock settling as the timed runs:
+    the stream rate the part reaches with no arithmetic, the practical ceiling of
+    an HBM-bound sweep."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    s0 = time.perf_counter()
+    while time.perf_counter() - s0 < SETTLE_S:
+        b.copy_(a)
+        torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def roofline(run, precision, order, ncell, copy_GBps=None):
     elem = 4 if precision == "fp32" else 8
     kern = {k: v for k, v in run["kernels"].items() if k.startswith("sweep") and v[1] > 0}
     dom = max(kern, key=lambda k: kern[k][0])
@@ -445,6 +471,22 @@ def roofline(run, precision, order, ncell):
     hbm["step_alg"] = {"bytes": alg_step, "GBps": round(alg_step / step_s / 1e9, 1),
                        "frac": round(alg_step / step_s / 1e9 / HBM_PEAK_GBS, 4)}
     prof = load_profile(precision, order)
+    if copy_GBps:
+        hbm["copy_GBps"] = round(copy_GBps, 1)
+        hbm["copy_frac_of_peak"] = round(copy_GBps / HBM_PEAK_GBS, 4)
+    # every sweep class of the step: counted bytes over its live launch time, against
+    # the peak and against the plain copy's rate
+    per_class = {}
+    for k, (kms, kl) in kern.items():
+        if k in prof and "bytes_per_launch" in prof[k]:
+            gbps = prof[k]["bytes_per_launch"] / (kms / kl * 1e-3) / 1e9
+            ent = {"ms_per_launch": round(kms / kl, 4), "counted_bytes_per_launch": prof[k]["bytes_per_launch"],
+                   "counted_GBps": round(gbps, 1), "counted_frac": round(gbps / HBM_PEAK_GBS, 4)}
+            if copy_GBps:
+                ent["of_copy_rate"] = round(gbps / copy_GBps, 4)
+            per_class[k] = ent
+    if per_class:
+        hbm["sweeps"] = per_class
     if all(k in prof and "bytes_per_launch" in prof[k] for k in kern):
         # every sweep class of the step, three launches each (one per stage)
         counted = 3.0 * sum(prof[k]["bytes_per_launch"] for k in kern)
@@ -567,6 +609,7 @@ def main():
     ncell = args.n ** 3
     print("bench: blob %d^3 WENO%d, %d warmup + %d timed steps" % (args.n, args.scheme, args.warmup,
                                                                   args.steps), file=sys.stderr, flush=True)
+    copy_GBps = copy_rate()
     r32 = run_gpu(spec, "fp32", args.steps, args.warmup)
     print("bench: fp32 %.4g cell-updates/s (%.3f ms/step)" % (r32["value"], r32["ms_per_step"]),
           file=sys.stderr, flush=True)
@@ -642,7 +685,7 @@ def main():
     w7 = side_leg("WENO7", weno7_leg) if args.scheme == 5 and not args.no_weno7 else None
     sch = side_leg("schemes", schemes_leg) if not args.no_schemes else None
     hub = side_leg("Hubble per-field errors", hubble_leg) if not args.no_hubble else None
-    dom, roof, hbm = roofline(r32, "fp32", args.scheme, ncell)
+    dom, roof, hbm = roofline(r32, "fp32", args.scheme, ncell, copy_GBps)
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
@@ -672,7 +715,7 @@ def main():
     if hub is not None:
         out["fp32_error_per_field"] = hub
     if r64 is not None:
-        _, roof64, hbm64 = roofline(r64, "fp64", args.scheme, ncell)
+        _, roof64, hbm64 = roofline(r64, "fp64", args.scheme, ncell, copy_GBps)
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                        "fp32_over_fp64": r32["value"] / r64["value"], "roofline": roof64, "hbm": hbm64,
                        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in r64["kernels"].items()}}

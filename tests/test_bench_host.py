@@ -47,11 +47,18 @@ def test_roofline_uses_profile_counters(monkeypatch):
     monkeypatch.setattr(bench, "load_profile", lambda precision, order=5: prof)
     monkeypatch.setattr(bench, "load_trace_avg", lambda kernel, precision, order=5: 0.255)
     n = 256 ** 3
-    _, roof, hbm = bench.roofline(fake_run(), "fp32", 5, n)
+    _, roof, hbm = bench.roofline(fake_run(), "fp32", 5, n, copy_GBps=5000.0)
     avg_s = 15.0 / 60 * 1e-3
     assert roof["traffic"] == 1.3e9
     assert hbm["counted_GBps"] == pytest.approx(1.3e9 / avg_s / 1e9, rel=1e-3)
     assert hbm["step_counted"]["bytes"] == pytest.approx(3 * 3.4e9)
+    # every sweep class against the peak and the plain copy's rate
+    assert hbm["copy_GBps"] == 5000.0 and hbm["copy_frac_of_peak"] == pytest.approx(0.625)
+    y = hbm["sweeps"]["sweep_y"]
+    assert y["ms_per_launch"] == pytest.approx(13.0 / 60, rel=1e-3)
+    assert y["counted_GBps"] == pytest.approx(1.1e9 / (13.0 / 60 * 1e-3) / 1e9, rel=1e-3)
+    assert y["of_copy_rate"] == pytest.approx(y["counted_GBps"] / 5000.0, rel=1e-3)
+    assert set(hbm["sweeps"]) == {"sweep_x", "sweep_y", "sweep_z"}
     assert roof["valu"]["wave_instr_per_cu_cycle_at_2.4GHz"] == pytest.approx(1.0e8 / 2.6e-4 / (256 * 2.4e9),
                                                                              rel=1e-3)
     assert roof["valu"]["wave_instr_per_cu_cycle"] == pytest.approx(1.0e8 / 2.6e-4 / (256 * 2.2e9), rel=1e-3)
