@@ -36,9 +36,10 @@ def primitives(spec, t, xyz=None):
     return out
 
 
-def ghost_mismatch(spec, t_end, ghosts):
-    """Largest n1 exp(-s/2) over the ghost layers (`ghosts` cells wide) for times
-    up to t_end: what the Hubble ghost cells, which carry n0 only, leave out."""
+def ghost_mismatch(spec, t_end):
+    """Largest n1 exp(-s/2) over the ghost cells for times up to t_end: what the
+    Hubble ghost cells, which carry n0 only, leave out.  s grows outwards and
+    falls with t, so the first ghost layer at t_end is the worst case."""
     n1, a, b, c = spec["ellipsoid"]
     nx, ny, nz = spec["shape"]
     worst = 0.0

@@ -474,7 +474,7 @@ def test_ellipsoidal_charge_L_truncation_order(orc):
         errs = []
         for n in (64, 128):
             spec = inputs.ellipsoidal(n=n, order=order, half_width=3.0, axes=(0.03, 0.035, 0.04))
-            assert ex.ghost_mismatch(spec, spec["t0"], 4) < 1e-12
+            assert ex.ghost_mismatch(spec, spec["t0"]) < 1e-12
             g = orc.grid_from_spec(spec)
             u = orc.prim2con(spec["prim"])
             L = orc.apply_L(g, u, t=spec["t0"])
