@@ -417,8 +417,8 @@ def hubble_field_errors(n=128, nsteps=100):
 def copy_rate(nbytes=1 << 30, reps=20):
     """Rate (GB/s, bytes read plus bytes written) of a plain device-to-device copy
     of 1 GiB, timed with events after the same clock settling as the timed runs:
-    the stream rate the part reaches with no arithmetic, the practical ceiling of
-    an HBM-bound sweep."""
+    the rate the part streams half reads, half writes with no arithmetic, a
+    reference for the HBM-bound sweeps (streams with fewer writes can exceed it)."""
     import torch
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
