@@ -94,6 +94,7 @@ MUTATIONS = [
      "double pm = ideal_pressure(g.gamma, E - M * mid, N);"),
     ("ideal recovery energy", "e = E - M * speed;", "e = E - M * speed * speed;"),
     ("ideal prim2con", "u[4] = n * std::sqrt(W2);", "u[4] = n * W2;"),
+    ("charge flux axis", "f[4] = u[4] * v[d];", "f[4] = u[4] * v[0];"),
 ]
 
 
