@@ -215,6 +215,26 @@ def test_blob_256_full_length(order, blob_specs):
     assert np.all(err32 <= 1e-5), err32
 
 
+@pytest.mark.parametrize("order", [5, 7])
+def test_blob_256_stage_path_equals_sweeps(order, blob_specs):
+    """The fused one-launch stage (the ensemble's kernel, and the benchmark's
+    schemes leg) and the directional sweeps (the single-grid default) at full
+    size over 20 graph-replayed FP32 steps: bitwise the same state."""
+    rh = rh_module()
+    spec = blob_specs[order]
+    out = {}
+    for path in (rh.RH_PATH_SWEEPS, rh.RH_PATH_STAGE):
+        h = gpu_hydro(spec, rh.RH_PREC_FP32)
+        rh.rh_set_path(h.plan, path)
+        rh.rh_set_graph(h.plan, 1)
+        h.step(spec["dt"], 20)
+        out[path] = h.get()
+        _, cnt = h.totals()
+        h.close()
+        assert cnt == [0, 0]
+    assert np.array_equal(out[rh.RH_PATH_SWEEPS], out[rh.RH_PATH_STAGE])
+
+
 def test_blob_256_adjoint_against_oracle(blob_specs, blob_oracle):
     """J(u)^T w at 256^3 in the launch configuration the benchmark's adjoint leg
     times (whole-row x kernel over 256-cell rows, y and z sweeps in 32-cell
