@@ -462,6 +462,51 @@ def test_hubble_run_accuracy(orc):
     assert errs[(7, 32)] < errs[(5, 32)]
 
 
+def test_ellipsoidal_solution_conserves_charge():
+    """The exact ellipsoidal solution used below (tests/ellipsoidal_exact.py),
+    checked against the charge conservation law itself: with N = n gamma, the
+    residual dN/dt + div(N v) by fourth-order central differences in t, x, y, z
+    vanishes to the differencing error at scattered points inside the light
+    cone, and the generated initial state is the solution at t0."""
+    import ellipsoidal_exact as ex
+    spec = inputs.ellipsoidal(n=16, half_width=3.0, axes=(0.05, 0.07, 0.09))
+    assert np.array_equal(spec["prim"], ex.primitives(spec, spec["t0"]))
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-3.0, 3.0, (3, 40))
+    t, h = 10.5, 1e-3
+
+    def N_and_flux(tt, X, Y, Z):
+        p = ex.primitives(spec, tt, (X, Y, Z))
+        gamma = 1.0 / np.sqrt(1.0 - (p[1] ** 2 + p[2] ** 2 + p[3] ** 2))
+        N = p[4] * gamma
+        return N, (N * p[1], N * p[2], N * p[3])
+
+    def d4(f):
+        return (8.0 * (f(h) - f(-h)) - (f(2 * h) - f(-2 * h))) / (12.0 * h)
+
+    X, Y, Z = pts
+    dNdt = d4(lambda e: N_and_flux(t + e, X, Y, Z)[0])
+    div = (d4(lambda e: N_and_flux(t, X + e, Y, Z)[1][0]) + d4(lambda e: N_and_flux(t, X, Y + e, Z)[1][1])
+           + d4(lambda e: N_and_flux(t, X, Y, Z + e)[1][2]))
+    scale = np.abs(dNdt).max()
+    assert np.abs(dNdt + div).max() < 1e-8 * max(scale, 1.0), (np.abs(dNdt + div).max(), scale)
+    # a wrong time dependence of the profile (s taken at t0 instead of t) breaks it
+    t0 = spec["hub"][0]
+
+    def frozen(tt, X, Y, Z):
+        p = ex.primitives(spec, tt, (X, Y, Z))
+        q = ex.primitives(spec, t0, (X, Y, Z))      # (t0/tau0)^3 F(s(t0))
+        r2 = X * X + Y * Y + Z * Z
+        p[4] = q[4] * ((t0 * t0 - r2) / (tt * tt - r2)) ** 1.5
+        gamma = 1.0 / np.sqrt(1.0 - (p[1] ** 2 + p[2] ** 2 + p[3] ** 2))
+        return p[4] * gamma, (p[4] * gamma * p[1], p[4] * gamma * p[2], p[4] * gamma * p[3])
+
+    dNdt_b = d4(lambda e: frozen(t + e, X, Y, Z)[0])
+    div_b = (d4(lambda e: frozen(t, X + e, Y, Z)[1][0]) + d4(lambda e: frozen(t, X, Y + e, Z)[1][1])
+             + d4(lambda e: frozen(t, X, Y, Z + e)[1][2]))
+    assert np.abs(dNdt_b + div_b).max() > 1e-4 * scale
+
+
 def test_ellipsoidal_charge_L_truncation_order(orc):
     """Exact ellipsoidal flow (the Hubble-like flow carrying an ellipsoidal
     charge, see tests/ellipsoidal_exact.py) with analytic boundary cells: the
